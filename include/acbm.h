@@ -1,0 +1,216 @@
+/*
+ * acbm.h -- libacbm: block-matching motion estimation with the adaptive cost
+ * block matching (ACBM) method on AMD Instinct MI355X (gfx950).
+ *
+ * Method: S. Lopez, G.M. Callico, J.F. Lopez, R. Sarmiento, "A High
+ * Quality/Low Computational Cost Technique for Block Matching Motion
+ * Estimation".  Every entry point below names the section it computes.
+ *
+ * Conventions shared by all calls
+ *  - Frames are 8-bit luma (Section 2.1: luminance values), row-major, with a
+ *    row pitch in bytes.  The current frame is cut into block_w x block_h
+ *    blocks (N x M, Section 1); block (r, c) starts at x = c*N, y = r*M.
+ *  - A candidate vector (u, v) with |u|, |v| <= p is evaluated only when the
+ *    displaced block lies wholly inside the reference frame (Section 1: the
+ *    search area is contained in the previous frame).  (0, 0) is always valid.
+ *  - SAD (Section 2.1, SAD equation) pairs the horizontal index with mv_x:
+ *    SAD(u,v) = sum_{j<M, i<N} |cur[y0+j][x0+i] - ref[y0+j+v][x0+i+u]|.
+ *  - Cost (Section 2.1): J = SAD + lambda * R, R = se(u - px) + se(v - py),
+ *    se(k) = bits of the signed Exp-Golomb codeword of k (1 for k = 0, else
+ *    2*floor(log2|k|) + 3), (px, py) the component-wise median of the final
+ *    vectors of the left, top and top-right blocks (left missing -> (0,0);
+ *    first block row -> top and top-right take the left value; last column ->
+ *    top-right is (0,0)).
+ *  - Minimum: smallest J, then smallest |u|+|v|, then the earlier window
+ *    position in raster order (v outer, top-left first).  Results are unique
+ *    and every call is bit-exact and deterministic.
+ *  - Device pointers are HIP device memory owned by the caller.  `stream` is
+ *    a hipStream_t (NULL = the null stream).  Calls are asynchronous on that
+ *    stream: argument errors return synchronously before anything is
+ *    enqueued; device failures surface on a later call or synchronisation.
+ *  - GPU layout requirements: frame pointers and pitch 4-byte aligned,
+ *    block_w and block_h in {8, 16}, p <= 127.  Other shapes the method allows
+ *    return ACBM_E_UNSUPPORTED.
+ */
+#ifndef ACBM_H
+#define ACBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ACBM_VERSION "0.1.0"
+
+/* ---- status codes ------------------------------------------------------ */
+#define ACBM_OK              0
+#define ACBM_E_INVAL        -1  /* null pointer, zero size, pitch < width, gamma_den = 0, bad enum */
+#define ACBM_E_SHAPE        -2  /* width % N, height % M, p > 127                       */
+#define ACBM_E_RANGE        -3  /* a cost or threshold would not fit the integer types  */
+#define ACBM_E_NOMEM        -4  /* workspace too small / request larger than the pool   */
+#define ACBM_E_DEVICE       -5  /* HIP error; detail in acbm_last_error()               */
+#define ACBM_E_BUSY         -6  /* server queue full                                    */
+#define ACBM_E_UNSUPPORTED  -7  /* valid for the method but not for this library/GPU    */
+#define ACBM_E_TIMEOUT      -8  /* a wait ended before its result was ready             */
+
+/* ---- searches and per-block outcomes ----------------------------------- */
+#define ACBM_ALGO_FSBM  0   /* full search over the (2p+1)^2 window (Section 2.3) */
+#define ACBM_ALGO_PBM   1   /* predictive search (Section 2.2)                    */
+#define ACBM_ALGO_ACBM  2   /* adaptive choice between the two (Section 3.2)      */
+
+#define ACBM_MODE_FSBM      0  /* full search                                  */
+#define ACBM_MODE_PBM_C1    1  /* ACBM kept PBM: Intra_SAD + SAD < alpha + beta*Qp^2 */
+#define ACBM_MODE_PBM_C2    2  /* ACBM kept PBM: SAD < gamma * Intra_SAD        */
+#define ACBM_MODE_CRITICAL  3  /* ACBM ran the full search                      */
+#define ACBM_MODE_PBM       4  /* plain PBM run                                 */
+
+/* workspace queries */
+#define ACBM_OP_SAD_TABLE  0
+#define ACBM_OP_FSBM       1
+#define ACBM_OP_PBM        2
+#define ACBM_OP_ACBM       3
+
+typedef struct acbm_geom {
+    uint32_t width, height;   /* pixels                                 */
+    uint32_t pitch;           /* bytes between rows, >= width           */
+    uint32_t block_w;         /* N: block width  (pairs with mv_x)      */
+    uint32_t block_h;         /* M: block height (pairs with mv_y)      */
+    uint32_t p;               /* maximum displacement per component     */
+} acbm_geom;
+
+/* lambda: Lagrange multiplier (Section 2.1); qp: quantisation step of the
+ * first ACBM test; alpha, beta, gamma = gamma_num/gamma_den: ACBM thresholds
+ * (Section 3.2; the paper's values for 16x16 blocks are 1000, 8, 1/4,
+ * Section 4). */
+typedef struct acbm_params {
+    uint32_t lambda, qp;
+    uint32_t alpha, beta;
+    uint32_t gamma_num, gamma_den;
+} acbm_params;
+
+typedef struct acbm_mv {
+    int16_t x, y;
+} acbm_mv;
+
+/* 32 bytes per block, row-major [by][bx]. */
+typedef struct acbm_block_result {
+    acbm_mv  mv;         /* chosen vector                                   */
+    uint32_t sad;        /* its SAD                                         */
+    uint32_t j;          /* its J = SAD + lambda*R                          */
+    uint32_t rate_bits;  /* its R                                           */
+    uint32_t cands;      /* candidate positions evaluated for this block   */
+    uint32_t mode;       /* ACBM_MODE_*                                     */
+    uint64_t intra_x;    /* N*M*Intra_SAD (exact; Section 3.1)              */
+} acbm_block_result;
+
+/* ---- library ------------------------------------------------------------ */
+const char* acbm_version(void);
+const char* acbm_strerror(int status);
+/* Detail of the last failing call on this thread ("" if none). */
+const char* acbm_last_error(void);
+/* Checks that the current HIP device is gfx950 (ACBM_E_UNSUPPORTED if not). */
+int acbm_init(void);
+
+/* Bytes of device workspace an operation needs for `npairs` frame pairs of
+ * this geometry (0 for ACBM_OP_SAD_TABLE).  Returns ACBM_E_* on bad geometry. */
+int acbm_workspace_size(int op, const acbm_geom* g, uint32_t npairs, size_t* bytes);
+
+/* Device-detected status of the last predictive (PBM/ACBM) run that used
+ * this workspace: 0 when every block finished, ACBM_E_TIMEOUT when a
+ * dependency wait gave up (the results are then incomplete).  Enqueues a
+ * small copy on `stream` and waits for the stream. */
+int acbm_workspace_status(const void* ws, size_t ws_bytes, void* stream, int* status);
+
+/* SAD table (Section 2.1, SAD equation; the full set of Section 2.3):
+ * table[r][c][v+p][u+p] (u32, [by][bx][2p+1][2p+1]) = SAD of block (r,c) at
+ * (u,v), or 0xFFFFFFFF where (u,v) is not a valid candidate.  No workspace. */
+int acbm_sad_table(const acbm_geom* g, const uint8_t* cur, const uint8_t* ref,
+                   uint32_t* table, void* stream);
+
+/* FSBM for one frame pair (Section 2.3 with the cost of Section 2.1):
+ * out[r][c] = the minimum of J over the valid window; cands = number of valid
+ * positions; mode = ACBM_MODE_FSBM. */
+int acbm_fsbm_frame(const acbm_geom* g, const acbm_params* prm, const uint8_t* cur,
+                    const uint8_t* ref, acbm_block_result* out, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/* PBM for one frame pair (Section 2.2).  Predictors: (0,0); the final vectors
+ * of the left, top-left, top, top-right blocks of this run; prev_field (the
+ * previous pair's vectors, [by][bx], NULL = all zero) at the co-located block
+ * and its 8 neighbours.  Predictors that are not valid candidates are dropped,
+ * repeats count once; the cheapest predictor is refined once over its valid
+ * integer 8-neighbours.  mode = ACBM_MODE_PBM. */
+int acbm_pbm_frame(const acbm_geom* g, const acbm_params* prm, const uint8_t* cur,
+                   const uint8_t* ref, const acbm_mv* prev_field, acbm_block_result* out,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* ACBM for one frame pair (Section 3.2): Intra_SAD, then PBM; PBM's vector is
+ * kept when Intra_SAD + SAD_PBM < alpha + beta*Qp^2 (mode 1) or else when
+ * SAD_PBM < gamma*Intra_SAD (mode 2); otherwise the block is critical and the
+ * full search runs with the same predictor (mode 3, cands = PBM's + window).
+ * Comparisons are exact (both sides scaled by N*M). */
+int acbm_acbm_frame(const acbm_geom* g, const acbm_params* prm, const uint8_t* cur,
+                    const uint8_t* ref, const acbm_mv* prev_field, acbm_block_result* out,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* ---- batches of sequences ----------------------------------------------- */
+/* A job is one sequence: frame t-1 is the reference of frame t, so nframes
+ * frames give nframes-1 pairs; PBM/ACBM take pair t-1's field as pair t's
+ * temporal neighbourhood (Section 2.2), zero for the first pair.  frames is a
+ * HOST array of nframes DEVICE pointers; out is device memory of
+ * (nframes-1)*by*bx results. */
+typedef struct acbm_job {
+    acbm_geom geom;
+    acbm_params params;
+    uint32_t algo;                 /* ACBM_ALGO_*                     */
+    uint32_t nframes;              /* >= 2                            */
+    const uint8_t* const* frames;  /* host array of device pointers   */
+    acbm_block_result* out;        /* device                          */
+} acbm_job;
+
+int acbm_batch_workspace_size(const acbm_job* jobs, size_t njobs, size_t* bytes);
+/* Runs every job; all work is enqueued on `stream` and the call returns
+ * without waiting.  Results are identical to running each pair through the
+ * *_frame calls in order. */
+int acbm_batch(const acbm_job* jobs, size_t njobs, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- serving ------------------------------------------------------------ */
+typedef struct acbm_serve_cfg {
+    size_t   pool_bytes;    /* device memory the server may own (frames, fields, workspace) */
+    uint32_t max_streams;   /* video streams that can be open at once      */
+    uint32_t max_inflight;  /* requests on the GPU at once                 */
+    uint32_t queue_depth;   /* requests waiting for admission              */
+} acbm_serve_cfg;
+
+typedef struct acbm_serve_stats {
+    uint64_t completed, rejected;
+    double   p50_us, p99_us, mean_us;   /* submit -> result ready            */
+    double   throughput_rps;            /* completed / (last done - first submit) */
+    double   gpu_busy_frac;             /* fraction of that span with work on the GPU */
+} acbm_serve_stats;
+
+typedef struct acbm_server acbm_server;
+
+int acbm_serve(const acbm_serve_cfg* cfg, acbm_server** out);
+/* Submits the next frame of a video stream (host memory, copied before the
+ * call returns).  The first frame of a stream only becomes its resident
+ * reference (the ticket completes with no results); every later frame is
+ * estimated against the stream's previous frame, which stays on the device.
+ * Returns ACBM_E_BUSY when the queue is full, ACBM_E_NOMEM when the request
+ * can never fit the pool. */
+int acbm_serve_submit(acbm_server* s, uint32_t stream_id, const uint8_t* host_frame,
+                      const acbm_geom* g, const acbm_params* prm, uint32_t algo,
+                      uint64_t* ticket);
+/* Waits for a ticket; copies by*bx results to host_out (may be NULL).
+ * timeout_us < 0 waits forever; ACBM_E_TIMEOUT if not ready in time. */
+int acbm_serve_wait(acbm_server* s, uint64_t ticket, acbm_block_result* host_out,
+                    int64_t timeout_us);
+int acbm_serve_stats_get(acbm_server* s, acbm_serve_stats* st);
+int acbm_serve_close(acbm_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

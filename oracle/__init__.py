@@ -79,6 +79,8 @@ def _bind(lib):
     lib.oracle_acbm_frame.argtypes = [P(_Geom), P(_Params), u8p, u8p, i16p, C.c_void_p]
     lib.oracle_sequence.argtypes = [P(_Geom), P(_Params), C.c_int, P(u8p), C.c_uint32,
                                     C.c_void_p]
+    lib.oracle_block.argtypes = [P(_Geom), P(_Params), C.c_int, u8p, u8p, i16p, P(C.c_int32),
+                                 P(C.c_int32), C.c_int, C.c_int, C.c_void_p]
     lib.oracle_sad_deviation.argtypes = [P(_Geom), u8p, u8p, C.c_int, C.c_int,
                                          P(C.c_uint64), P(C.c_uint32)]
     return lib
@@ -246,6 +248,22 @@ def sequence(frames, block_w, block_h, p, params: Params, algo: int, width=None)
     out = np.zeros((len(frames) - 1, by, bx), dtype=result_dtype())
     _check(_load().oracle_sequence(C.byref(g), C.byref(params._c()), algo, arr, len(frames),
                                    out.ctypes.data))
+    return out
+
+
+def block(cur, ref, block_w, block_h, p, params: Params, algo: int, field_x, field_y, r, c,
+          prev_field=None, width=None) -> np.ndarray:
+    """One block's result given the final vectors of the blocks before it
+    (field_x/field_y, [by, bx]) and the previous field."""
+    cur, ref = _frame(cur), _frame(ref)
+    g = geom(cur, block_w, block_h, p, width)
+    fx = np.ascontiguousarray(field_x, dtype=np.int32)
+    fy = np.ascontiguousarray(field_y, dtype=np.int32)
+    keep, pfp = _field_ptr(prev_field)
+    out = np.zeros((), dtype=result_dtype())
+    _check(_load().oracle_block(C.byref(g), C.byref(params._c()), algo, _u8p(cur), _u8p(ref), pfp,
+                                fx.ctypes.data_as(C.POINTER(C.c_int32)),
+                                fy.ctypes.data_as(C.POINTER(C.c_int32)), r, c, out.ctypes.data))
     return out
 
 

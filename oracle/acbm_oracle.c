@@ -400,6 +400,23 @@ static void pbm_block(const oracle_geom* g, const oracle_params* prm,
     *cands = (uint32_t)n;
 }
 
+/* ACBM decision (Section 3.2) for a block with Intra_SAD = intra/(N*M) and
+ * PBM result SAD sad_p.  First test: Intra_SAD + SAD_PBM < alpha + beta*Qp^2;
+ * second test: SAD_PBM < gamma * Intra_SAD.  Both are multiplied through by
+ * N*M (and gamma_den) so that Intra_SAD stays exact.  Returns 1 or 2 for the
+ * test that kept PBM, 3 for a critical block. */
+static int acbm_decide(const oracle_geom* g, const oracle_params* prm, uint64_t intra,
+                       uint32_t sad_p)
+{
+    u128 nm = (u128)g->block_w * g->block_h;
+    u128 t1 = (u128)prm->alpha + (u128)prm->beta * prm->qp * prm->qp;
+    int c1 = (u128)intra + nm * sad_p < nm * t1;
+    int c2 = (u128)prm->gamma_den * nm * sad_p < (u128)prm->gamma_num * intra;
+    if (c1) return 1;
+    if (c2) return 2;
+    return 3;
+}
+
 /* Shared frame loop of the PBM and ACBM runs. */
 static int predictive_frame(const oracle_geom* g, const oracle_params* prm,
                             const uint8_t* cur, const uint8_t* ref,
@@ -410,7 +427,6 @@ static int predictive_frame(const oracle_geom* g, const oracle_params* prm,
     if ((rc = check_params(prm))) return rc;
     if (!cur || !ref || !out) return ORACLE_EINVAL;
     int bx = blocks_x(g), by = blocks_y(g);
-    u128 nm = (u128)g->block_w * g->block_h;
     int32_t* fx = calloc((size_t)bx * by, sizeof(int32_t));
     int32_t* fy = calloc((size_t)bx * by, sizeof(int32_t));
     if (!fx || !fy) {
@@ -431,17 +447,9 @@ static int predictive_frame(const oracle_geom* g, const oracle_params* prm,
             if (!acbm) {
                 store(o, &pbm, cands, 4, intra);
             } else {
-                /* first test: Intra_SAD + SAD_PBM < alpha + beta*Qp^2, both
-                 * sides multiplied by N*M so that Intra_SAD stays exact */
-                u128 t1 = (u128)prm->alpha + (u128)prm->beta * prm->qp * prm->qp;
-                int c1 = (u128)intra + nm * pbm.sad < nm * t1;
-                /* second test: SAD_PBM < gamma * Intra_SAD, multiplied by
-                 * N*M*gamma_den */
-                int c2 = (u128)prm->gamma_den * nm * pbm.sad < (u128)prm->gamma_num * intra;
-                if (c1) {
-                    store(o, &pbm, cands, 1, intra);
-                } else if (c2) {
-                    store(o, &pbm, cands, 2, intra);
+                int mode = acbm_decide(g, prm, intra, pbm.sad);
+                if (mode != 3) {
+                    store(o, &pbm, cands, (uint32_t)mode, intra);
                 } else {
                     /* critical block: full search with the same predictor */
                     cand_eval fs;
@@ -455,6 +463,43 @@ static int predictive_frame(const oracle_geom* g, const oracle_params* prm,
     }
     free(fx);
     free(fy);
+    return ORACLE_OK;
+}
+
+int oracle_block(const oracle_geom* g, const oracle_params* prm, int algo,
+                 const uint8_t* cur, const uint8_t* ref, const int16_t* prev_field,
+                 const int32_t* field_x, const int32_t* field_y, int r, int c,
+                 oracle_result* out)
+{
+    int rc = oracle_check_geom(g);
+    if (rc) return rc;
+    if ((rc = check_params(prm))) return rc;
+    if (!cur || !ref || !field_x || !field_y || !out) return ORACLE_EINVAL;
+    if (r < 0 || c < 0 || r >= blocks_y(g) || c >= blocks_x(g)) return ORACLE_EINVAL;
+    int px, py;
+    oracle_median_pred(field_x, field_y, blocks_x(g), r, c, &px, &py);
+    uint64_t intra = oracle_intra_x(g, cur, r, c);
+    if (algo == ORACLE_FSBM) {
+        cand_eval best;
+        uint32_t count = full_search(g, prm, cur, ref, r, c, px, py, &best);
+        store(out, &best, count, 0, intra);
+        return ORACLE_OK;
+    }
+    cand_eval pbm;
+    uint32_t npbm;
+    pbm_block(g, prm, cur, ref, prev_field, field_x, field_y, r, c, px, py, &pbm, &npbm);
+    if (algo == ORACLE_PBM) {
+        store(out, &pbm, npbm, 4, intra);
+        return ORACLE_OK;
+    }
+    int mode = acbm_decide(g, prm, intra, pbm.sad);
+    if (mode != 3) {
+        store(out, &pbm, npbm, (uint32_t)mode, intra);
+    } else {
+        cand_eval whole;
+        uint32_t nwin = full_search(g, prm, cur, ref, r, c, px, py, &whole);
+        store(out, &whole, npbm + nwin, 3, intra);
+    }
     return ORACLE_OK;
 }
 

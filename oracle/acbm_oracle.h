@@ -100,6 +100,15 @@ int oracle_sequence(const oracle_geom* g, const oracle_params* prm, int algo,
                     const uint8_t* const* frames, uint32_t nframes,
                     oracle_result* out);
 
+/* One block of a raster run, given the final vectors of the blocks before it
+ * (field_x/field_y, [by][bx], only entries before (r, c) are read) and the
+ * previous field: the block's FSBM (algo 0), PBM (1) or ACBM (2) result.
+ * Used to check single blocks of frames too large for a whole raster run. */
+int oracle_block(const oracle_geom* g, const oracle_params* prm, int algo,
+                 const uint8_t* cur, const uint8_t* ref, const int16_t* prev_field,
+                 const int32_t* field_x, const int32_t* field_y, int r, int c,
+                 oracle_result* out);
+
 /* Sum of |SAD(u,v) - SAD_min| over the valid window of one block
  * (Section 3.1, SAD_deviation) and the SAD minimum itself. */
 int oracle_sad_deviation(const oracle_geom* g, const uint8_t* cur, const uint8_t* ref,

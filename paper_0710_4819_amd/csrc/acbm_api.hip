@@ -1,0 +1,262 @@
+// acbm_api.hip -- C ABI of libacbm: argument checks, plans, workspace sizing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "acbm_device.h"
+#include "acbm_internal.h"
+
+namespace acbm {
+
+static thread_local std::string t_last_error;
+
+int fail(int code, const std::string& msg) {
+  t_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  t_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return ACBM_E_DEVICE;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int se_bits_host(int k) {
+  unsigned a = (unsigned)(k < 0 ? -k : k);
+  if (a == 0) return 1;
+  int fl = 31 - __builtin_clz(a);
+  return 2 * fl + 3;
+}
+
+int rate_max(int p) { return 2 * se_bits_host(2 * p); }
+
+int check_geom(const acbm_geom* g, KGeom* k) {
+  if (!g) return fail(ACBM_E_INVAL, "geometry is NULL");
+  if (!g->width || !g->height || !g->block_w || !g->block_h)
+    return fail(ACBM_E_INVAL, "zero frame or block size");
+  if (g->pitch < g->width) return fail(ACBM_E_INVAL, "pitch smaller than width");
+  if (g->width % g->block_w || g->height % g->block_h)
+    return fail(ACBM_E_SHAPE, "frame size is not a multiple of the block size");
+  if (g->p > 127) return fail(ACBM_E_SHAPE, "p above 127");
+  if ((g->block_w != 8 && g->block_w != 16) || (g->block_h != 8 && g->block_h != 16))
+    return fail(ACBM_E_UNSUPPORTED, "block_w and block_h must be 8 or 16");
+  if (g->pitch % 4) return fail(ACBM_E_UNSUPPORTED, "pitch must be a multiple of 4 bytes");
+  if ((uint64_t)g->pitch * g->height > (1ull << 31))
+    return fail(ACBM_E_UNSUPPORTED, "frame larger than 2 GiB");
+  if (k) {
+    k->width = (int)g->width;
+    k->height = (int)g->height;
+    k->pitch = (int)g->pitch;
+    k->bw = (int)g->block_w;
+    k->bh = (int)g->block_h;
+    k->p = (int)g->p;
+    k->bx = k->width / k->bw;
+    k->by = k->height / k->bh;
+    k->nb = k->bx * k->by;
+  }
+  return ACBM_OK;
+}
+
+int check_params(const acbm_params* prm, const KGeom& k) {
+  if (!prm) return fail(ACBM_E_INVAL, "params is NULL");
+  if (prm->gamma_den == 0) return fail(ACBM_E_INVAL, "gamma_den is zero");
+  const uint64_t jmax = 255ull * k.bw * k.bh + (uint64_t)prm->lambda * rate_max(k.p);
+  if (jmax >= (1ull << 32)) return fail(ACBM_E_RANGE, "lambda too large: J would not fit 32 bits");
+  return ACBM_OK;
+}
+
+int check_frame_ptr(const void* p, const char* what) {
+  if (!p) return fail(ACBM_E_INVAL, std::string(what) + " is NULL");
+  if ((uintptr_t)p % 4) return fail(ACBM_E_UNSUPPORTED, std::string(what) + " is not 4-byte aligned");
+  return ACBM_OK;
+}
+
+int check_device() {
+  static std::mutex mu;
+  static int known_dev = -1, known_rc = 0;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(mu);
+  if (dev == known_dev) return known_rc;
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  known_dev = dev;
+  known_rc = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0
+                 ? ACBM_OK
+                 : fail(ACBM_E_UNSUPPORTED, std::string("device is ") + prop.gcnArchName +
+                                                ", this library is built for gfx950");
+  return known_rc;
+}
+
+// Issue cost of one V_QSAD_PK_U16_U8 relative to a full-rate VALU op, used by
+// the planner (ACBM_QSAD_COST overrides it for tuning experiments).
+static double qsad_cost() {
+  static double c = [] {
+    const char* e = std::getenv("ACBM_QSAD_COST");
+    return e ? std::atof(e) : 1.0;
+  }();
+  return c;
+}
+
+// Choose the candidate rows per lane R and the workgroup size.  Model per
+// wave-task, in CU clocks: VALU = R*M*N/4 QSADs; LDS = (R+M-1) window rows of
+// 2N bytes per lane at 128 B/clk; the slower of the two bounds the task.
+// With max_threads = 1024 every task gets its own thread (the full-search
+// kernel keeps all SADs of a block in registers); otherwise tasks loop over
+// a fixed group of max_threads.
+SearchPlan plan_search(int N, int M, int p, int max_threads) {
+  static const int Rs[] = {1, 2, 3, 4, 5, 6, 8, 11, 16};
+  const char* force = std::getenv("ACBM_R");
+  SearchPlan best{0, 0, 0};
+  double best_cost = 1e300;
+  for (int R : Rs) {
+    if (force && std::atoi(force) != R) continue;
+    WindowShape s;
+    if (N == 16 && M == 16) s = window_shape<16, 16>(p, R);
+    else if (N == 16 && M == 8) s = window_shape<16, 8>(p, R);
+    else if (N == 8 && M == 16) s = window_shape<8, 16>(p, R);
+    else s = window_shape<8, 8>(p, R);
+    const int tasks = s.quads * s.groups;
+    const int lds = s.rows * s.stride * 4;
+    int threads, rounds;
+    if (max_threads >= 1024) {
+      if (tasks > 1024) continue;
+      threads = (tasks + 63) / 64 * 64;
+      rounds = 1;
+    } else {
+      threads = max_threads;
+      rounds = (tasks + threads - 1) / threads;
+    }
+    if (lds > 64 * 1024) continue;
+    const double valu = (double)R * M * (N / 4) * qsad_cost();
+    const double ldsc = (double)(R + M - 1) * N;
+    const double cost = (double)(threads / 64) * rounds * (std::max(valu, ldsc) + 8.0 * R);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = SearchPlan{R, threads, lds};
+    }
+  }
+  if (!best.R) best = SearchPlan{16, 1024, 0};
+  return best;
+}
+
+}  // namespace acbm
+
+using namespace acbm;
+
+extern "C" {
+
+const char* acbm_version(void) { return ACBM_VERSION; }
+
+const char* acbm_strerror(int s) {
+  switch (s) {
+    case ACBM_OK: return "ok";
+    case ACBM_E_INVAL: return "invalid argument";
+    case ACBM_E_SHAPE: return "frame/block/search shape not allowed by the method";
+    case ACBM_E_RANGE: return "value out of range for the integer cost";
+    case ACBM_E_NOMEM: return "not enough workspace or pool memory";
+    case ACBM_E_DEVICE: return "HIP device error";
+    case ACBM_E_BUSY: return "queue full";
+    case ACBM_E_UNSUPPORTED: return "not supported by this library or device";
+    case ACBM_E_TIMEOUT: return "timed out";
+    default: return "unknown status";
+  }
+}
+
+const char* acbm_last_error(void) { return t_last_error.c_str(); }
+
+int acbm_init(void) {
+  t_last_error.clear();
+  return check_device();
+}
+
+int acbm_workspace_size(int op, const acbm_geom* g, uint32_t npairs, size_t* bytes) {
+  KGeom k;
+  int rc = check_geom(g, &k);
+  if (rc) return rc;
+  if (!bytes) return fail(ACBM_E_INVAL, "bytes is NULL");
+  if (npairs == 0) return fail(ACBM_E_INVAL, "npairs is zero");
+  switch (op) {
+    case ACBM_OP_SAD_TABLE: *bytes = 0; return ACBM_OK;
+    case ACBM_OP_FSBM: *bytes = fsbm_ws_bytes(k, npairs); return ACBM_OK;
+    case ACBM_OP_PBM:
+    case ACBM_OP_ACBM: *bytes = predictive_ws_bytes(k, npairs); return ACBM_OK;
+    default: return fail(ACBM_E_INVAL, "unknown operation");
+  }
+}
+
+int acbm_workspace_status(const void* ws, size_t ws_bytes, void* stream, int* status) {
+  if (!ws || !status) return fail(ACBM_E_INVAL, "workspace or status is NULL");
+  if (ws_bytes < sizeof(WsHeader)) return fail(ACBM_E_NOMEM, "workspace too small");
+  WsHeader h;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(&h, ws, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "reading the workspace header");
+  *status = h.status == 0 ? ACBM_OK : ACBM_E_TIMEOUT;
+  return ACBM_OK;
+}
+
+int acbm_sad_table(const acbm_geom* g, const uint8_t* cur, const uint8_t* ref, uint32_t* table,
+                   void* stream) {
+  KGeom k;
+  int rc = check_geom(g, &k);
+  if (rc) return rc;
+  if ((rc = check_frame_ptr(cur, "cur")) || (rc = check_frame_ptr(ref, "ref"))) return rc;
+  if (!table) return fail(ACBM_E_INVAL, "table is NULL");
+  if ((rc = check_device())) return rc;
+  return launch_sad_table(k, cur, ref, table, static_cast<hipStream_t>(stream));
+}
+
+int acbm_fsbm_frame(const acbm_geom* g, const acbm_params* prm, const uint8_t* cur,
+                    const uint8_t* ref, acbm_block_result* out, void* ws, size_t ws_bytes,
+                    void* stream) {
+  KGeom k;
+  int rc = check_geom(g, &k);
+  if (rc) return rc;
+  if ((rc = check_params(prm, k))) return rc;
+  if ((rc = check_frame_ptr(cur, "cur")) || (rc = check_frame_ptr(ref, "ref"))) return rc;
+  if (!out || !ws) return fail(ACBM_E_INVAL, "out or workspace is NULL");
+  if ((rc = check_device())) return rc;
+  const uint8_t* frames[2] = {ref, cur};
+  return launch_fsbm(k, *prm, frames, 1, ws, ws_bytes, out, static_cast<hipStream_t>(stream));
+}
+
+static int predictive_frame(int algo, const acbm_geom* g, const acbm_params* prm,
+                            const uint8_t* cur, const uint8_t* ref, const acbm_mv* prev,
+                            acbm_block_result* out, void* ws, size_t ws_bytes, void* stream) {
+  KGeom k;
+  int rc = check_geom(g, &k);
+  if (rc) return rc;
+  if ((rc = check_params(prm, k))) return rc;
+  if ((rc = check_frame_ptr(cur, "cur")) || (rc = check_frame_ptr(ref, "ref"))) return rc;
+  if (!out || !ws) return fail(ACBM_E_INVAL, "out or workspace is NULL");
+  if ((rc = check_device())) return rc;
+  const uint8_t* frames[2] = {ref, cur};
+  return launch_predictive(k, *prm, algo, frames, 1, prev, ws, ws_bytes, out,
+                           static_cast<hipStream_t>(stream));
+}
+
+int acbm_pbm_frame(const acbm_geom* g, const acbm_params* prm, const uint8_t* cur,
+                   const uint8_t* ref, const acbm_mv* prev_field, acbm_block_result* out,
+                   void* ws, size_t ws_bytes, void* stream) {
+  return predictive_frame(ACBM_ALGO_PBM, g, prm, cur, ref, prev_field, out, ws, ws_bytes,
+                          stream);
+}
+
+int acbm_acbm_frame(const acbm_geom* g, const acbm_params* prm, const uint8_t* cur,
+                    const uint8_t* ref, const acbm_mv* prev_field, acbm_block_result* out,
+                    void* ws, size_t ws_bytes, void* stream) {
+  return predictive_frame(ACBM_ALGO_ACBM, g, prm, cur, ref, prev_field, out, ws, ws_bytes,
+                          stream);
+}
+
+}  // extern "C"

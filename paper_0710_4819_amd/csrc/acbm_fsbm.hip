@@ -1,0 +1,426 @@
+// acbm_fsbm.hip -- SAD table and full search (FSBM) kernels for gfx950.
+//
+// Full search (Section 2.3) costs (2p+1)^2 SADs (Section 2.1, SAD equation)
+// per block; that is where the time goes.  It is split in two kernels:
+//
+//  k_search  one workgroup per block.  The block's search window is staged
+//            in LDS, the current block sits in scalar registers, and every
+//            lane computes four horizontally adjacent candidates x R rows
+//            with V_QSAD_PK_U16_U8.  Output: either the whole table
+//            (acbm_sad_table) or, for FSBM, the block's SAD minimum and the
+//            few candidates that can still win once the rate term is added.
+//  k_resolve one workgroup per frame pair.  The predictor of a block depends
+//            on the final vectors of its left, top and top-right neighbours,
+//            so the argmin of J is sequential in raster order; the kernel
+//            resolves every block as soon as those three are known (blocks
+//            with a single possible winner need no predictor at all).
+//
+// Pruning bound (exact): R >= 2 for every candidate and R <= Rmax =
+// 2*se(2p), so the winner has J <= SAD_min + lambda*Rmax while any candidate
+// has J >= SAD + 2*lambda; only candidates with
+// SAD <= SAD_min + lambda*(Rmax - 2) can win (ties included).
+#include <hip/hip_runtime.h>
+
+#include "acbm_device.h"
+#include "acbm_internal.h"
+
+namespace acbm {
+
+// Workgroups are dispatched round-robin over the 8 XCDs.  Remap so that each
+// XCD gets one contiguous band of blocks: neighbouring blocks share most of
+// their search windows, and a band then stays in one XCD's L2.
+__device__ __forceinline__ int xcd_band(int wg, int n) {
+  const int per = (n + 7) >> 3;
+  return (wg & 7) * per + (wg >> 3);
+}
+
+// IntraX (Section 3.1, Intra_SAD scaled by N*M) of the block at (x0, y0),
+// computed by one wave.  Every lane of the wave gets the value.
+template <int N, int M>
+__device__ __forceinline__ uint32_t wave_intra_x(const uint8_t* __restrict__ cur, int pitch,
+                                                 int x0, int y0) {
+  constexpr int D = M * N / 4;  // dwords in the block (<= 64)
+  const int lane = threadIdx.x & 63;
+  uint32_t d = 0;
+  if (lane < D) {
+    const int j = lane / (N / 4), k = lane % (N / 4);
+    d = *reinterpret_cast<const uint32_t*>(cur + (size_t)(y0 + j) * pitch + x0 + 4 * k);
+  }
+  const uint32_t s = wave_sum_u32(__builtin_amdgcn_sad_u8(d, 0u, 0u));
+  uint32_t a = 0;
+  if (lane < D) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int q = (int)(N * M) * (int)((d >> (8 * b)) & 0xFF) - (int)s;
+      a += (uint32_t)(q < 0 ? -q : q);
+    }
+  }
+  return wave_sum_u32(a);
+}
+
+// ---------------------------------------------------------------------------
+// Window search.  kTable: write the u32 table; else: write BlockRec + overflow.
+// ---------------------------------------------------------------------------
+template <int N, int M, int R, bool kTable>
+__global__ void __launch_bounds__(1024)
+k_search(const KGeom g, const WindowShape s, const FramePtrs fr, uint32_t* __restrict__ table,
+         BlockRec* __restrict__ recs, uint16_t* __restrict__ ovf, uint32_t slack) {
+  extern __shared__ uint32_t win[];
+  __shared__ uint64_t red[16];
+  __shared__ uint32_t n_keep;
+
+  const int b = xcd_band(blockIdx.x, g.nb);
+  if (b >= g.nb) return;
+  const int pair = blockIdx.y;
+  const uint8_t* __restrict__ ref = fr.f[pair];
+  const uint8_t* __restrict__ cur = fr.f[pair + 1];
+  const int r = b / g.bx, c = b - r * g.bx;
+  const int x0 = c * N, y0 = r * M;
+  const int p = s.p, W = 2 * p + 1;
+
+  load_window<N, M>(win, s, ref, g.pitch, g.width, g.height, x0, y0);
+  CurBlock<N, M> cb;
+  load_cur_uniform<N, M>(cb, cur, g.pitch, x0, y0);
+  uint32_t intra = 0;
+  if (!kTable && threadIdx.x < 64) intra = wave_intra_x<N, M>(cur, g.pitch, x0, y0);
+  if (threadIdx.x == 0) n_keep = 0;
+  __syncthreads();
+
+  const int tasks = s.quads * s.groups;
+  const int t = threadIdx.x;
+  const bool active = t < tasks;
+  const int q = active ? t % s.quads : 0;
+  const int gi = active ? t / s.quads : 0;
+  uint64_t acc[R];
+  if (active) task_sads<N, M, R>(win, s.stride, q, gi, cb, acc);
+
+  const int u0 = s.u_lo + 4 * q, v0 = -p + R * gi;
+  if (kTable) {
+    if (!active) return;
+    uint32_t* out = table + (size_t)b * W * W;
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      const int v = v0 + rr;
+      if (v > p) break;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int u = u0 + i;
+        if (u < -p || u > p) continue;
+        const uint32_t sad = (uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu;
+        out[(v + p) * W + (u + p)] =
+            cand_valid(u, v, p, x0, y0, N, M, g.width, g.height) ? sad : 0xFFFFFFFFu;
+      }
+    }
+    return;
+  }
+
+  // ---- FSBM: SAD minimum and the candidates that can still win ----------
+  uint32_t lmin = 0xFFFFFFFFu;
+  if (active) {
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int u = u0 + i, v = v0 + rr;
+        if (cand_valid(u, v, p, x0, y0, N, M, g.width, g.height))
+          lmin = min(lmin, (uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu);
+      }
+  }
+  const uint32_t smin = (uint32_t)group_min_u64(lmin, red);
+  const uint64_t thr = (uint64_t)smin + slack;
+
+  BlockRec* rec = recs + ((size_t)pair * g.nb + b);
+  if (active) {
+    uint32_t mine = 0;
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int u = u0 + i, v = v0 + rr;
+        const uint32_t sad = (uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu;
+        if (cand_valid(u, v, p, x0, y0, N, M, g.width, g.height) && sad <= thr) ++mine;
+      }
+    if (mine) {
+      uint32_t slot = atomicAdd(&n_keep, mine);
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int u = u0 + i, v = v0 + rr;
+          const uint32_t sad = (uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu;
+          if (cand_valid(u, v, p, x0, y0, N, M, g.width, g.height) && sad <= thr) {
+            if (slot < (uint32_t)kShort)
+              rec->e[slot] = (sad << 16) | (uint32_t)((v + p) * W + (u + p));
+            ++slot;
+          }
+        }
+    }
+  }
+  __syncthreads();
+  const uint32_t total = n_keep;
+  if (total > (uint32_t)kShort && active) {
+    uint16_t* row = ovf + ((size_t)pair * g.nb + b) * (size_t)(W * W);
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      const int v = v0 + rr;
+      if (v > p) break;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int u = u0 + i;
+        if (u < -p || u > p) continue;
+        const uint32_t sad = (uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu;
+        row[(v + p) * W + (u + p)] =
+            cand_valid(u, v, p, x0, y0, N, M, g.width, g.height) ? (uint16_t)sad : (uint16_t)0xFFFF;
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    rec->sad_min = smin;
+    rec->count = total;
+    rec->intra_x = intra;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FSBM resolve: argmin of J = SAD + lambda*R per block, in dependency order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void window_uv(uint32_t ras, int p, int* u, int* v) {
+  const int W = 2 * p + 1;
+  *v = (int)(ras / (uint32_t)W) - p;
+  *u = (int)(ras % (uint32_t)W) - p;
+}
+
+// Cheapest candidate of one block given its predictor.
+__device__ uint64_t block_argmin(const BlockRec* __restrict__ rec,
+                                 const uint16_t* __restrict__ row, int p, int px, int py,
+                                 uint32_t lam) {
+  uint64_t best = ~0ull;
+  const uint32_t n = rec->count;
+  if (n <= (uint32_t)kShort) {
+    for (uint32_t k = 0; k < n; ++k) {
+      const uint32_t e = rec->e[k];
+      int u, v;
+      window_uv(e & 0xFFFFu, p, &u, &v);
+      const uint32_t j = (e >> 16) + lam * (se_bits(u - px) + se_bits(v - py));
+      const uint64_t key = make_key(j, u, v, p);
+      best = key < best ? key : best;
+    }
+  } else {
+    const int W = 2 * p + 1;
+    for (int ras = 0; ras < W * W; ++ras) {
+      const uint32_t sad = row[ras];
+      if (sad == 0xFFFFu) continue;
+      int u, v;
+      window_uv((uint32_t)ras, p, &u, &v);
+      const uint32_t j = sad + lam * (se_bits(u - px) + se_bits(v - py));
+      const uint64_t key = make_key(j, u, v, p);
+      best = key < best ? key : best;
+    }
+  }
+  return best;
+}
+
+__device__ __forceinline__ uint32_t sad_of(const BlockRec* __restrict__ rec,
+                                           const uint16_t* __restrict__ row, uint32_t ras) {
+  const uint32_t n = rec->count;
+  if (n > (uint32_t)kShort) return row[ras];
+  for (uint32_t k = 0; k < n; ++k)
+    if ((rec->e[k] & 0xFFFFu) == ras) return rec->e[k] >> 16;
+  return 0xFFFFFFFFu;  // unreachable: the winner is always in the list
+}
+
+// Predictor of block b from the packed vectors in `mvs`; false if one of the
+// neighbours it needs is not decided yet.
+__device__ __forceinline__ bool median_pred(const uint16_t* mvs, int b, int r, int c, int bx,
+                                            int* px, int* py) {
+  uint16_t A = pack_mv(0, 0), B, C;
+  if (c > 0) {
+    A = mvs[b - 1];
+    if (A == kMvUnset) return false;
+  }
+  if (r == 0) {
+    B = A;
+    C = A;
+  } else {
+    B = mvs[b - bx];
+    C = (c == bx - 1) ? pack_mv(0, 0) : mvs[b - bx + 1];
+    if (B == kMvUnset || C == kMvUnset) return false;
+  }
+  *px = med3(mv_x(A), mv_x(B), mv_x(C));
+  *py = med3(mv_y(A), mv_y(B), mv_y(C));
+  return true;
+}
+
+// The decided vectors live in LDS when they fit (mv_global == nullptr), else
+// in a workspace array; either way only this workgroup touches them.
+__global__ void __launch_bounds__(1024)
+k_resolve(const KGeom g, const BlockRec* __restrict__ recs, const uint16_t* __restrict__ ovf,
+          acbm_block_result* __restrict__ out, uint32_t lam, uint16_t* mv_global) {
+  extern __shared__ uint16_t mv_lds[];
+  __shared__ int pending;
+  const int pair = blockIdx.x;
+  const int p = g.p, W = 2 * p + 1, nb = g.nb, bx = g.bx;
+  uint16_t* mvs = mv_global ? mv_global + (size_t)pair * nb : mv_lds;
+  recs += (size_t)pair * nb;
+  ovf += (size_t)pair * nb * (size_t)(W * W);
+  out += (size_t)pair * nb;
+
+  // blocks with a single possible winner are decided without a predictor
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    uint16_t m = kMvUnset;
+    if (recs[b].count == 1) {
+      int u, v;
+      window_uv(recs[b].e[0] & 0xFFFFu, p, &u, &v);
+      m = pack_mv(u, v);
+    }
+    mvs[b] = m;
+  }
+  __syncthreads();
+
+  // sweep until every block is decided; each sweep decides at least the
+  // first undecided block in raster order, whose neighbours all precede it,
+  // so nb sweeps always suffice
+  for (int sweep = 0; sweep <= nb; ++sweep) {
+    if (threadIdx.x == 0) pending = 0;
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      if (mvs[b] != kMvUnset) continue;
+      const int r = b / bx, c = b - r * bx;
+      int px, py;
+      if (!median_pred(mvs, b, r, c, bx, &px, &py)) {
+        pending = 1;
+        continue;
+      }
+      const uint64_t key = block_argmin(recs + b, ovf + (size_t)b * (W * W), p, px, py, lam);
+      int u = 0, v = 0;
+      if (key != ~0ull) window_uv((uint32_t)(key & 0xFFFFu), p, &u, &v);
+      mvs[b] = pack_mv(u, v);
+    }
+    __syncthreads();
+    const int again = pending;
+    __syncthreads();
+    if (!again) break;
+  }
+
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const int r = b / bx, c = b - r * bx;
+    int px, py;
+    median_pred(mvs, b, r, c, bx, &px, &py);
+    const int u = mv_x(mvs[b]), v = mv_y(mvs[b]);
+    const uint32_t ras = (uint32_t)((v + p) * W + (u + p));
+    const uint32_t sad = sad_of(recs + b, ovf + (size_t)b * (W * W), ras);
+    const uint32_t rate = se_bits(u - px) + se_bits(v - py);
+    acbm_block_result res;
+    res.mv.x = (int16_t)u;
+    res.mv.y = (int16_t)v;
+    res.sad = sad;
+    res.j = sad + lam * rate;
+    res.rate_bits = rate;
+    res.cands = valid_count(p, c * g.bw, r * g.bh, g.bw, g.bh, g.width, g.height);
+    res.mode = ACBM_MODE_FSBM;
+    res.intra_x = recs[b].intra_x;
+    out[b] = res;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side: plans and launches.
+// ---------------------------------------------------------------------------
+#define ACBM_R_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(11) X(16)
+
+template <int N, int M, bool kTable>
+static int launch_search_nm(const KGeom& g, const SearchPlan& pl, const FramePtrs& fr,
+                            int npairs, uint32_t* table, BlockRec* recs, uint16_t* ovf,
+                            uint32_t slack, hipStream_t st) {
+  const WindowShape s = window_shape<N, M>(g.p, pl.R);
+  const int grid_x = ((g.nb + 7) / 8) * 8;
+  dim3 grid(grid_x, npairs), block(pl.threads);
+  switch (pl.R) {
+#define ACBM_CASE(RR)                                                                         \
+  case RR:                                                                                    \
+    hipLaunchKernelGGL((k_search<N, M, RR, kTable>), grid, block, pl.lds_bytes, st, g, s, fr, \
+                       table, recs, ovf, slack);                                              \
+    break;
+    ACBM_R_LIST(ACBM_CASE)
+#undef ACBM_CASE
+    default:
+      return fail(ACBM_E_UNSUPPORTED, "no search kernel for this row blocking");
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ACBM_OK : hip_fail(e, "launching the window search");
+}
+
+template <bool kTable>
+static int launch_search(const KGeom& g, const FramePtrs& fr, int npairs, uint32_t* table,
+                         BlockRec* recs, uint16_t* ovf, uint32_t slack, hipStream_t st) {
+  const SearchPlan pl = plan_search(g.bw, g.bh, g.p);
+  if (g.bw == 16 && g.bh == 16)
+    return launch_search_nm<16, 16, kTable>(g, pl, fr, npairs, table, recs, ovf, slack, st);
+  if (g.bw == 16 && g.bh == 8)
+    return launch_search_nm<16, 8, kTable>(g, pl, fr, npairs, table, recs, ovf, slack, st);
+  if (g.bw == 8 && g.bh == 16)
+    return launch_search_nm<8, 16, kTable>(g, pl, fr, npairs, table, recs, ovf, slack, st);
+  if (g.bw == 8 && g.bh == 8)
+    return launch_search_nm<8, 8, kTable>(g, pl, fr, npairs, table, recs, ovf, slack, st);
+  return fail(ACBM_E_UNSUPPORTED, "block size must be 8 or 16 in each direction");
+}
+
+int launch_sad_table(const KGeom& g, const uint8_t* cur, const uint8_t* ref, uint32_t* table,
+                     hipStream_t st) {
+  FramePtrs fr{};
+  fr.f[0] = ref;
+  fr.f[1] = cur;
+  return launch_search<true>(g, fr, 1, table, nullptr, nullptr, 0, st);
+}
+
+static size_t ovf_row_bytes(const KGeom& g) {
+  const size_t W = 2 * (size_t)g.p + 1;
+  return W * W * sizeof(uint16_t);
+}
+
+// Vectors of the resolve kernel stay in LDS up to this many bytes.
+constexpr size_t kResolveLdsMax = 48 * 1024;
+
+size_t fsbm_ws_bytes(const KGeom& g, uint32_t npairs) {
+  const size_t mv_bytes = (size_t)g.nb * sizeof(uint16_t) > kResolveLdsMax
+                              ? align256((size_t)npairs * g.nb * sizeof(uint16_t))
+                              : 0;
+  return align256(sizeof(WsHeader)) + align256((size_t)npairs * g.nb * sizeof(BlockRec)) +
+         align256((size_t)npairs * g.nb * ovf_row_bytes(g)) + mv_bytes;
+}
+
+int launch_fsbm(const KGeom& g, const acbm_params& prm, const uint8_t* const* frames,
+                uint32_t npairs, void* ws, size_t ws_bytes, acbm_block_result* out,
+                hipStream_t st) {
+  if (ws_bytes < fsbm_ws_bytes(g, npairs)) return fail(ACBM_E_NOMEM, "workspace too small");
+  char* base = static_cast<char*>(ws);
+  BlockRec* recs = reinterpret_cast<BlockRec*>(base + align256(sizeof(WsHeader)));
+  uint16_t* ovf = reinterpret_cast<uint16_t*>(
+      base + align256(sizeof(WsHeader)) + align256((size_t)npairs * g.nb * sizeof(BlockRec)));
+  const bool mv_in_lds = (size_t)g.nb * sizeof(uint16_t) <= kResolveLdsMax;
+  uint16_t* mv_ws = mv_in_lds ? nullptr
+                              : reinterpret_cast<uint16_t*>(
+                                    base + align256(sizeof(WsHeader)) +
+                                    align256((size_t)npairs * g.nb * sizeof(BlockRec)) +
+                                    align256((size_t)npairs * g.nb * ovf_row_bytes(g)));
+  const uint64_t slack64 = (uint64_t)prm.lambda * (uint64_t)(rate_max(g.p) - 2);
+  const uint32_t slack = slack64 > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)slack64;
+  for (uint32_t p0 = 0; p0 < npairs; p0 += kMaxPairsPerLaunch) {
+    const int n = (int)std::min<uint32_t>(kMaxPairsPerLaunch, npairs - p0);
+    FramePtrs fr{};
+    for (int k = 0; k <= n; ++k) fr.f[k] = frames[p0 + k];
+    BlockRec* r = recs + (size_t)p0 * g.nb;
+    uint16_t* o = ovf + (size_t)p0 * g.nb * (ovf_row_bytes(g) / 2);
+    int rc = launch_search<false>(g, fr, n, nullptr, r, o, slack, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_resolve, dim3(n), dim3(1024),
+                       mv_in_lds ? (size_t)g.nb * sizeof(uint16_t) : 0, st, g, r, o,
+                       out + (size_t)p0 * g.nb, prm.lambda,
+                       mv_in_lds ? nullptr : mv_ws + (size_t)p0 * g.nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "launching the FSBM resolve");
+  }
+  return ACBM_OK;
+}
+
+}  // namespace acbm

@@ -1,0 +1,84 @@
+// acbm_internal.h -- host-side declarations shared by the libacbm sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/acbm.h"
+
+namespace acbm {
+
+// Geometry as the kernels see it.
+struct KGeom {
+  int width, height, pitch;
+  int bw, bh, p;
+  int bx, by, nb;
+};
+
+// Per-block record written by the full-search pass for the FSBM resolve:
+// the block's SAD minimum, how many candidates can still win (their SAD is
+// within lambda*(Rmax-2) of the minimum, see the pruning bound in the
+// resolve kernel), IntraX, and up to kShort of those candidates packed as
+// (SAD << 16 | window raster index).  When more than kShort can win the
+// block's full row of SADs is kept in the overflow table instead.
+constexpr int kShort = 28;
+struct BlockRec {
+  uint32_t sad_min, count, intra_x, pad;
+  uint32_t e[kShort];
+};
+static_assert(sizeof(BlockRec) == 128, "record is two cache lines of 64 B");
+
+// Frame pointers of one launch: pair k uses f[k] as reference and f[k+1] as
+// current frame.
+constexpr int kMaxPairsPerLaunch = 64;
+struct FramePtrs {
+  const uint8_t* f[kMaxPairsPerLaunch + 1];
+};
+
+// Launch plan of the window search for one (N, M, p).
+struct SearchPlan {
+  int R;        // candidate rows per lane
+  int threads;  // workgroup size (multiple of 64, >= tasks)
+  int lds_bytes;
+};
+
+// Workspace layout (all offsets 256-byte aligned).
+struct WsHeader {
+  uint32_t status;      // 0 ok, else a device-detected failure code
+  uint32_t ticket;      // work counter of the dataflow kernel
+  uint32_t pad[62];
+};
+static_assert(sizeof(WsHeader) == 256, "header is 256 bytes");
+
+constexpr uint32_t kStatusSpinTimeout = 1;
+
+size_t align256(size_t x);
+int rate_max(int p);  // 2 * se_bits(2p)
+
+// Set the thread's error detail and return `code`.
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+// Validation shared by every entry point.
+int check_geom(const acbm_geom* g, KGeom* k);
+int check_params(const acbm_params* prm, const KGeom& k);
+int check_frame_ptr(const void* p, const char* what);
+int check_device();
+
+SearchPlan plan_search(int N, int M, int p, int max_threads = 1024);
+
+// Launchers (acbm_kernels.hip).  All enqueue on `s` and return ACBM_* codes.
+int launch_sad_table(const KGeom& g, const uint8_t* cur, const uint8_t* ref, uint32_t* table,
+                     hipStream_t s);
+size_t fsbm_ws_bytes(const KGeom& g, uint32_t npairs);
+int launch_fsbm(const KGeom& g, const acbm_params& prm, const uint8_t* const* frames,
+                uint32_t npairs, void* ws, size_t ws_bytes, acbm_block_result* out,
+                hipStream_t s);
+size_t predictive_ws_bytes(const KGeom& g, uint32_t npairs);
+int launch_predictive(const KGeom& g, const acbm_params& prm, int algo,
+                      const uint8_t* const* frames, uint32_t npairs, const acbm_mv* prev_field,
+                      void* ws, size_t ws_bytes, acbm_block_result* out, hipStream_t s);
+
+}  // namespace acbm

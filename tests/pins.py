@@ -528,3 +528,24 @@ if __name__ == "__main__":
     bad = run_all(sys.argv[1] if len(sys.argv) > 1 else None)
     print(" ".join(bad) if bad else "all pins hold")
     sys.exit(1 if bad else 0)
+
+
+def pin_block_matches_raster():
+    """The single-block entry point reproduces every block of whole raster
+    runs when handed the final vectors of the blocks before it."""
+    cur, ref = _acbm_inputs()
+    prev = _prev_for(cur, 16, 16, 5, 91)
+    prm = oracle.Params(lam=3, qp=3, alpha=150, beta=1)
+    for algo, run in ((oracle.FSBM, lambda: oracle.fsbm_frame(cur, ref, 16, 16, 5, prm)),
+                      (oracle.PBM, lambda: oracle.pbm_frame(cur, ref, 16, 16, 5, prm, prev)),
+                      (oracle.ACBM, lambda: oracle.acbm_frame(cur, ref, 16, 16, 5, prm, prev))):
+        res = run()
+        by, bx = res.shape
+        for r in range(by):
+            for c in range(bx):
+                one = oracle.block(cur, ref, 16, 16, 5, prm, algo, res["mv_x"], res["mv_y"], r, c,
+                                   prev_field=None if algo == oracle.FSBM else prev)
+                assert one == res[r, c], (algo, r, c)
+
+
+ALL_PINS.append(pin_block_matches_raster)

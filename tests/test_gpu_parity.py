@@ -1,0 +1,231 @@
+"""GPU parity: libacbm against the CPU oracle, bit-exact on every field.
+
+Every case prints what it runs before touching the GPU, so a failure on the
+box names its inputs.  Whole frames are compared element by element where the
+oracle finishes in seconds; at the 1920x1088, p = 32 size (the benchmark's
+launch configuration) a sample of blocks is checked one by one with the
+oracle's single-block entry, given the GPU's own neighbouring vectors.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_0710_4819_amd import acbm, synth
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("mv_x", "mv_y", "sad", "j", "rate_bits", "cands", "mode", "intra_x")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(a: np.ndarray, pitch: int | None = None) -> torch.Tensor:
+    """Frame to the GPU, optionally inside a wider pitch filled with junk."""
+    h, w = a.shape
+    if pitch is None or pitch == w:
+        return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    big = synth.rng(4242).integers(0, 256, size=(h, pitch)).astype(np.uint8)
+    big[:, :w] = a
+    return torch.from_numpy(big).cuda()
+
+
+def same(gpu: np.ndarray, ref: np.ndarray, what: str):
+    assert gpu.shape == ref.shape, what
+    for f in FIELDS:
+        g = gpu[f].astype(np.int64)
+        o = ref[f].astype(np.int64)
+        if not np.array_equal(g, o):
+            bad = np.argwhere(g != o)
+            i = tuple(bad[0])
+            raise AssertionError(f"{what}: field {f} differs at {len(bad)} blocks, first {i}: "
+                                 f"gpu {gpu[i]} oracle {ref[i]}")
+
+
+def oparams(p: acbm.Params) -> oracle.Params:
+    return oracle.Params(lam=p.lam, qp=p.qp, alpha=p.alpha, beta=p.beta,
+                         gamma_num=p.gamma_num, gamma_den=p.gamma_den)
+
+
+def frames_noise(h, w, seed, hi=256):
+    g = synth.rng(seed)
+    return g.integers(0, hi, size=(h, w)).astype(np.uint8), g.integers(0, hi, size=(h, w)).astype(np.uint8)
+
+
+def frames_tex(h, w, seed, shift=(2, -3)):
+    ref = synth.texture(h, w, 1.5, synth.rng(seed))
+    cur = synth.add_noise(np.roll(ref, shift, (0, 1)), 2.0, synth.rng(seed + 1))
+    return cur, ref
+
+
+# (name, cur, ref, bw, bh, p, pitch)
+def table_cases():
+    wl = synth.planted_blocks()
+    yield "planted_qcif_16x16_p7", wl.frames[1], wl.frames[0], 16, 16, 7, None
+    c, r = frames_tex(48, 64, 11)
+    yield "tex_8x8_p5_pitch80", c, r, 8, 8, 5, 80
+    c, r = frames_tex(32, 48, 12)
+    yield "tex_16x8_p3", c, r, 16, 8, 3, None
+    yield "tex_8x16_p6", c, r, 8, 16, 6, None
+    yield "tex_16x16_p0", c, r, 16, 16, 0, None
+    c, r = frames_noise(64, 64, 13, hi=3)
+    yield "levels_16x16_p20", c, r, 16, 16, 20, None
+    c, r = frames_tex(48, 64, 14)
+    yield "tex_16x16_p127_max", c, r, 16, 16, 127, None
+    c, r = frames_tex(96, 128, 15, shift=(5, 9))
+    yield "tex_8x8_p32", c, r, 8, 8, 32, None
+
+
+@pytest.mark.parametrize("case", list(table_cases()), ids=lambda c: c[0])
+def test_sad_table(case):
+    name, cur, ref, bw, bh, p, pitch = case
+    say(f"sad_table {name}: {cur.shape} block {bw}x{bh} p={p} pitch={pitch}")
+    w = cur.shape[1]
+    got = acbm.table_to_numpy(acbm.sad_table(dev(cur, pitch), dev(ref, pitch), bw, bh, p, width=w))
+    torch.cuda.synchronize()
+    want = oracle.sad_table(cur, ref, bw, bh, p)
+    assert np.array_equal(got, want), f"{name}: {np.count_nonzero(got != want)} entries differ"
+
+
+def search_cases():
+    wl = synth.planted_blocks()
+    yield "planted_qcif_l4", wl.frames[1], wl.frames[0], 16, 16, 7, 4, None
+    yield "planted_qcif_l0", wl.frames[1], wl.frames[0], 16, 16, 7, 0, None
+    yield "planted_qcif_l32", wl.frames[1], wl.frames[0], 16, 16, 7, 32, None
+    c, r = frames_tex(64, 80, 21)
+    yield "tex_8x8_p6_l8_pitch96", c, r, 8, 8, 6, 8, 96
+    c = np.full((48, 64), 90, np.uint8)
+    r = np.full((48, 64), 91, np.uint8)
+    yield "flat_16x16_p9_l2", c, r, 16, 16, 9, 2, None     # every candidate ties: overflow rows
+    c, r = frames_noise(48, 64, 22, hi=4)
+    yield "levels_16x8_p4_l1", c, r, 16, 8, 4, 1, None      # many ties
+    c, r = frames_tex(48, 48, 23, shift=(0, 0))
+    yield "tex_8x16_p11_l3", c, r, 8, 16, 11, 3, None
+    sc = synth.cif_scene(nframes=2, lam=32)
+    yield "cif_scene_p16_l32", sc.frames[1], sc.frames[0], 16, 16, 16, 32, None
+
+
+@pytest.mark.parametrize("case", list(search_cases()), ids=lambda c: c[0])
+def test_fsbm_frame(case):
+    name, cur, ref, bw, bh, p, lam, pitch = case
+    say(f"fsbm {name}: {cur.shape} block {bw}x{bh} p={p} lambda={lam}")
+    prm = acbm.Params(lam=lam, qp=lam)
+    w = cur.shape[1]
+    got = acbm.to_numpy(acbm.fsbm_frame(dev(cur, pitch), dev(ref, pitch), bw, bh, p, prm, width=w))
+    want = oracle.fsbm_frame(cur, ref, bw, bh, p, oparams(prm))
+    same(got, want, f"fsbm {name}")
+
+
+def predictive_params():
+    yield "paper", lambda bw, bh, lam: acbm.default_params(bw, bh, lam)
+    yield "mixed", lambda bw, bh, lam: acbm.Params(lam=lam, qp=lam, alpha=bw * bh, beta=1,
+                                                    gamma_num=1, gamma_den=3)
+    yield "all_critical", lambda bw, bh, lam: acbm.Params(lam=lam, qp=lam, alpha=0, beta=0,
+                                                          gamma_num=0, gamma_den=1)
+
+
+@pytest.mark.parametrize("algo", ["pbm", "acbm"])
+@pytest.mark.parametrize("pp", list(predictive_params()), ids=lambda x: x[0])
+@pytest.mark.parametrize("case", list(search_cases()), ids=lambda c: c[0])
+def test_predictive_frame(case, pp, algo):
+    name, cur, ref, bw, bh, p, lam, pitch = case
+    if algo == "pbm" and pp[0] != "paper":
+        pytest.skip("PBM does not read the thresholds")
+    prm = pp[1](bw, bh, lam)
+    by, bx = cur.shape[0] // bh, cur.shape[1] // bw
+    prev = synth.rng(77).integers(-p, p + 1, size=(by, bx, 2)).astype(np.int16)
+    say(f"{algo} {name} {pp[0]}: {cur.shape} block {bw}x{bh} p={p} {prm}")
+    w = cur.shape[1]
+    fn = acbm.pbm_frame if algo == "pbm" else acbm.acbm_frame
+    ofn = oracle.pbm_frame if algo == "pbm" else oracle.acbm_frame
+    for pf in (None, prev):
+        ws = acbm.workspace(acbm.OP_ACBM, acbm.geom(dev(cur, pitch), bw, bh, p, w), "cuda")
+        got_t = fn(dev(cur, pitch), dev(ref, pitch), bw, bh, p, prm,
+                   prev_field=None if pf is None else torch.from_numpy(pf).cuda(), width=w, ws=ws)
+        assert acbm.workspace_status(ws) == 0
+        got = acbm.to_numpy(got_t)
+        want = ofn(cur, ref, bw, bh, p, oparams(prm), prev_field=pf)
+        same(got, want, f"{algo} {name} {pp[0]} prev={'yes' if pf is not None else 'no'}")
+
+
+@pytest.mark.parametrize("algo", [acbm.ALGO_FSBM, acbm.ALGO_PBM, acbm.ALGO_ACBM])
+def test_batch_sequences(algo):
+    """Several sequences of uneven geometry in one call equal the oracle's
+    sequence runs (pair t takes pair t-1's field)."""
+    seqs = []
+    sc = synth.cif_scene(nframes=5, lam=8)
+    seqs.append(([f[:144, :176].copy() for f in sc.frames], 16, 16, 7, 8))
+    seqs.append(([f[:96, :128].copy() for f in sc.frames[:4]], 8, 8, 5, 4))
+    seqs.append(([f[:64, :96].copy() for f in sc.frames[:3]], 16, 8, 9, 2))
+    b = acbm.Batch("cuda")
+    for frames, bw, bh, p, lam in seqs:
+        prm = acbm.default_params(bw, bh, lam)
+        b.add([dev(f) for f in frames], bw, bh, p, prm, algo)
+    say(f"batch algo={algo}: {len(seqs)} sequences")
+    outs = b.run()
+    torch.cuda.synchronize()
+    for k, (frames, bw, bh, p, lam) in enumerate(seqs):
+        prm = acbm.default_params(bw, bh, lam)
+        want = oracle.sequence(frames, bw, bh, p, oparams(prm), algo)
+        same(acbm.to_numpy(outs[k]), want, f"batch seq {k} algo {algo}")
+
+
+def test_long_sequence_crosses_launch_chunks():
+    """More pairs than one launch takes: the temporal field must carry over."""
+    sc = synth.cif_scene(nframes=70, lam=8)
+    frames = [f[:48, :64].copy() for f in sc.frames]
+    prm = acbm.default_params(16, 16, 8)
+    for algo in (acbm.ALGO_ACBM, acbm.ALGO_FSBM):
+        say(f"long sequence algo={algo}: {len(frames)} frames 64x48")
+        b = acbm.Batch("cuda")
+        b.add([dev(f) for f in frames], 16, 16, 6, prm, algo)
+        got = acbm.to_numpy(b.run()[0])
+        want = oracle.sequence(frames, 16, 16, 6, oparams(prm), algo)
+        same(got, want, f"long sequence algo {algo}")
+
+
+def _sample_blocks(by, bx, n, seed):
+    g = synth.rng(seed)
+    pts = {(0, 0), (0, bx - 1), (by - 1, 0), (by - 1, bx - 1), (by // 2, bx // 2)}
+    while len(pts) < n:
+        pts.add((int(g.integers(0, by)), int(g.integers(0, bx))))
+    return sorted(pts)
+
+
+@pytest.mark.parametrize("algo", [acbm.ALGO_FSBM, acbm.ALGO_ACBM])
+def test_full_size_hd_sampled(algo):
+    """1920x1088, 16x16, p = 32, lambda = 8: three pairs of the moving scene
+    in the launch configuration the benchmark times; IntraX on every block,
+    and 24 blocks per pair recomputed by the oracle from the GPU's own
+    neighbouring vectors."""
+    sc = synth.hd_scene(nframes=4)
+    prm = acbm.default_params(16, 16, 8)
+    b = acbm.Batch("cuda")
+    b.add([dev(f) for f in sc.frames], 16, 16, 32, prm, algo)
+    say(f"hd sampled algo={algo}")
+    got = acbm.to_numpy(b.run()[0])
+    for t in range(len(sc.frames) - 1):
+        cur, ref = sc.frames[t + 1], sc.frames[t]
+        ix = oracle.intra_table(cur, 16, 16)
+        assert np.array_equal(got[t]["intra_x"].astype(np.uint64), ix)
+        prev = None if t == 0 or algo == acbm.ALGO_FSBM else oracle.field_of(got[t - 1]).astype(np.int16)
+        if algo == acbm.ALGO_ACBM and t == 0:
+            prev = np.zeros(got.shape[1:] + (2,), np.int16)
+        for (r, c) in _sample_blocks(*got.shape[1:], 24, 100 + t):
+            one = oracle.block(cur, ref, 16, 16, 32, oparams(prm), algo, got[t]["mv_x"],
+                               got[t]["mv_y"], r, c, prev_field=prev)
+            for f in FIELDS:
+                assert int(one[f]) == int(got[t][r, c][f]), (t, r, c, f, one, got[t][r, c])
+
+
+def test_deterministic_repeat():
+    sc = synth.cif_scene(nframes=4, lam=8)
+    prm = acbm.default_params(16, 16, 8)
+    runs = []
+    for _ in range(3):
+        b = acbm.Batch("cuda")
+        b.add([dev(f) for f in sc.frames], 16, 16, 16, prm, acbm.ALGO_ACBM)
+        runs.append(acbm.to_numpy(b.run()[0]))
+    assert np.array_equal(runs[0], runs[1]) and np.array_equal(runs[0], runs[2])

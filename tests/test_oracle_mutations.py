@@ -45,11 +45,12 @@ MUTATIONS = [
     ("pbm_temporal_colocated_only", "for (int dr = -1; dr <= 1; dr++) {\n        for (int dc = -1; dc <= 1; dc++) {\n            int rr = r + dr, cc = c + dc;\n            if (rr < 0 || rr >= by",
      "for (int dr = 0; dr <= 0; dr++) {\n        for (int dc = 0; dc <= 0; dc++) {\n            int rr = r + dr, cc = c + dc;\n            if (rr < 0 || rr >= by"),
     ("pbm_no_ring", "if (du == 0 && dv == 0) continue;\n            int u = b0.u", "continue;\n            int u = b0.u"),
-    ("c1_le", "int c1 = (u128)intra + nm * pbm.sad < nm * t1;",
-     "int c1 = (u128)intra + nm * pbm.sad <= nm * t1;"),
+    ("c1_le", "int c1 = (u128)intra + nm * sad_p < nm * t1;",
+     "int c1 = (u128)intra + nm * sad_p <= nm * t1;"),
     ("c1_qp_linear", "(u128)prm->beta * prm->qp * prm->qp", "(u128)prm->beta * prm->qp"),
-    ("c2_gamma_swapped", "(u128)prm->gamma_den * nm * pbm.sad < (u128)prm->gamma_num * intra",
-     "(u128)prm->gamma_num * nm * pbm.sad < (u128)prm->gamma_den * intra"),
+    ("c2_gamma_swapped", "(u128)prm->gamma_den * nm * sad_p < (u128)prm->gamma_num * intra",
+     "(u128)prm->gamma_num * nm * sad_p < (u128)prm->gamma_den * intra"),
+    ("c1_before_c2", "    if (c1) return 1;\n    if (c2) return 2;", "    if (c2) return 2;\n    if (c1) return 1;"),
     ("critical_zero_pred", "uint32_t n = full_search(g, prm, cur, ref, r, c, px, py, &fs);",
      "uint32_t n = full_search(g, prm, cur, ref, r, c, 0, 0, &fs);"),
     ("critical_count", "store(o, &fs, cands + n, 3, intra);", "store(o, &fs, n, 3, intra);"),
