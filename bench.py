@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark: ACBM motion estimation on one MI355X.
+
+Workload (the paper's method at HD size): a 60-frame 1920x1088 u8 luma
+sequence from the seeded moving-scene generator (panned blurred-noise
+background, 16 textured rectangles with velocities up to +-24 px/frame,
+sigma = 2 noise), 16x16 blocks, p = 32, lambda = Qp = 8, the paper's
+alpha = 1000, beta = 8, gamma = 1/4.  The 59 frame pairs are resident in HBM
+before timing starts.
+
+One step = the whole hot path over the sequence: full search (FSBM: SAD
+window search + J argmin) for all 59 pairs, then ACBM (Intra_SAD, PBM,
+the two tests, critical full searches) for all 59 pairs with the temporal
+field carried from pair to pair.
+
+value = algorithmic candidate-pixel SAD evaluations per second of the step:
+one evaluation is one |cur - ref| accumulated for one pixel of one valid
+candidate; FSBM counts #valid * N*M per block and ACBM counts its returned
+`cands` * N*M per block.  Out-of-frame lanes the kernels compute and mask are
+not counted.
+
+The roofline object covers the dominant kernel (the window search): its
+algorithmic evaluations per launch divided by its mean launch time, measured
+with HIP events on its own stream, against the packed-SAD VALU peak.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+METRIC = "candidate-pixel SAD evals/s + 1080p p=32 frames/s (FSBM vs ACBM), % VALU peak"
+# 256 CUs x 64 lanes x 2.4 GHz x 4 absolute differences per lane-clock:
+# V_SAD_U8 (4 per op, full rate) and V_QSAD_PK_U16_U8 (16 per op, quarter
+# rate) reach the same byte rate.
+PEAK_TEVALS = 256 * 64 * 2.4e9 * 4 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--frames", type=int, default=60)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only", choices=["fsbm", "acbm"], default=None,
+                    help="time only one of the two searches (profiling runs)")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, prm_oracle):
+    """The plain C oracle (one thread) on a bounded sample: FSBM and ACBM of
+    the first frame pair of the same sequence."""
+    import oracle
+    cur, ref = wl.frames[1], wl.frames[0]
+    t0 = time.perf_counter()
+    f = oracle.fsbm_frame(cur, ref, 16, 16, 32, prm_oracle)
+    a = oracle.acbm_frame(cur, ref, 16, 16, 32, prm_oracle)
+    dt = time.perf_counter() - t0
+    evals = (int(f["cands"].astype(np.int64).sum()) + int(a["cands"].astype(np.int64).sum())) * 256
+    return {"value": evals / dt, "unit": "candidate-pixel SAD evals/s", "cores": 1, "kind": "oracle",
+            "sample": "FSBM + ACBM of pair 1 of the 1920x1088 p=32 sequence, single thread, "
+                      f"{dt:.1f} s, {evals / 1e9:.2f} G evals",
+            "seconds": round(dt, 2)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_0710_4819_amd import acbm, synth
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    wl = synth.hd_scene(nframes=args.frames, lam=8)
+    frames = [torch.from_numpy(f).to(dev) for f in wl.frames]
+    prm = acbm.default_params(16, 16, 8)
+    npairs = len(frames) - 1
+    stream = torch.cuda.Stream(device=dev)
+
+    fs = acbm.Batch(dev)
+    fs_out = fs.add(frames, 16, 16, 32, prm, acbm.ALGO_FSBM)
+    ac = acbm.Batch(dev)
+    ac_out = ac.add(frames, 16, 16, 32, prm, acbm.ALGO_ACBM)
+    ws_f = torch.empty(fs.workspace_size(), dtype=torch.uint8, device=dev)
+    ws_a = torch.empty(max(256, ac.workspace_size()), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    do_f = args.only in (None, "fsbm")
+    do_a = args.only in (None, "acbm")
+
+    def step(evs=None):
+        if evs:
+            evs[0].record(stream)
+        if do_f:
+            fs.run(ws_f, stream)
+        if evs:
+            evs[1].record(stream)
+        if do_a:
+            ac.run(ws_a, stream)
+        if evs:
+            evs[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if do_a:
+        assert acbm.workspace_status(ws_a, stream) == 0, "ACBM dependency wait timed out"
+
+    acbm.profile_enable(True)
+    acbm.profile_reset()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    search_ms, search_n = acbm.profile_read("search")
+    resolve_ms, resolve_n = acbm.profile_read("resolve")
+    pred_ms, pred_n = acbm.profile_read("predictive")
+    acbm.profile_enable(False)
+
+    ms_step = wall * 1e3 / args.steps
+    ms_f = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    ms_a = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+
+    res_f = acbm.to_numpy(fs_out) if do_f else None
+    res_a = acbm.to_numpy(ac_out) if do_a else None
+    nm = 256
+    ev_f = int(res_f["cands"].astype(np.int64).sum()) * nm if do_f else 0
+    ev_a = int(res_a["cands"].astype(np.int64).sum()) * nm if do_a else 0
+    out = {
+        "metric": METRIC,
+        "value": (ev_f + ev_a) / (ms_step / 1e3),
+        "unit": "candidate-pixel SAD evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"hd_scene_1920x1088_{args.frames}f_16x16_p32_lambda8", "frames": args.frames,
+                   "pairs": npairs, "block": "16x16", "p": 32, "lambda": 8, "qp": 8,
+                   "alpha": prm.alpha, "beta": prm.beta, "gamma": "1/4", "timed": args.only or "fsbm+acbm"},
+    }
+    if do_f:
+        out["fsbm"] = {"ms": ms_f, "frames_per_s": npairs / (ms_f / 1e3), "evals": ev_f,
+                       "evals_per_s": ev_f / (ms_f / 1e3),
+                       "search_ms_per_launch": search_ms / max(1, search_n),
+                       "resolve_ms_per_launch": resolve_ms / max(1, resolve_n)}
+    if do_a:
+        modes = np.bincount(res_a["mode"].ravel(), minlength=5)
+        out["acbm"] = {"ms": ms_a, "frames_per_s": npairs / (ms_a / 1e3), "evals": ev_a,
+                       "evals_per_s": ev_a / (ms_a / 1e3),
+                       "cands_per_block": float(res_a["cands"].mean()),
+                       "critical_frac": float(modes[3] / modes.sum()),
+                       "mode_counts": {"c1": int(modes[1]), "c2": int(modes[2]), "critical": int(modes[3])},
+                       "predictive_ms_per_launch": pred_ms / max(1, pred_n),
+                       "speedup_vs_fsbm": (ms_f / ms_a) if do_f else None}
+    if do_f and search_n:
+        per_launch = ev_f / (search_n / args.steps)  # one search launch covers all 59 pairs
+        achieved = per_launch / (search_ms / search_n / 1e3) / 1e12
+        out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_TEVALS,
+                           "unit": "T evals/s", "frac": achieved / PEAK_TEVALS, "traffic": None,
+                           "kernel": "k_search (FSBM window search, QSAD)",
+                           "launch_ms": search_ms / search_n}
+    if not args.no_cpu:
+        import oracle
+        out["cpu_baseline"] = cpu_baseline(wl, oracle.Params(lam=prm.lam, qp=prm.qp, alpha=prm.alpha,
+                                                             beta=prm.beta, gamma_num=prm.gamma_num,
+                                                             gamma_den=prm.gamma_den))
+        out["cpu_baseline"]["host"] = platform.processor() or platform.machine()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -176,6 +176,17 @@ int acbm_batch_workspace_size(const acbm_job* jobs, size_t njobs, size_t* bytes)
  * *_frame calls in order. */
 int acbm_batch(const acbm_job* jobs, size_t njobs, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- kernel timing ------------------------------------------------------ */
+/* When enabled, every kernel the library launches is bracketed by HIP events
+ * on the stream it runs on.  acbm_profile_read waits for the recorded events
+ * and returns the summed device time and the launch count of one kernel
+ * since the last reset.  Kernel names: "search" (window search, all block
+ * sizes), "resolve" (FSBM argmin), "predictive" (PBM/ACBM), "setup"
+ * (predictive workspace set-up), "field" (served field extraction). */
+int acbm_profile_enable(int on);
+int acbm_profile_reset(void);
+int acbm_profile_read(const char* kernel, double* total_ms, uint64_t* launches);
+
 /* ---- serving ------------------------------------------------------------ */
 typedef struct acbm_serve_cfg {
     size_t   pool_bytes;    /* device memory the server may own (frames, fields, workspace) */

@@ -106,6 +106,8 @@ def lib():
         L.acbm_acbm_frame.argtypes = [P(Geom), P(CParams), vp, vp, vp, vp, vp, sz, vp]
         L.acbm_batch_workspace_size.argtypes = [P(Job), sz, P(sz)]
         L.acbm_batch.argtypes = [P(Job), sz, vp, sz, vp]
+        L.acbm_profile_enable.argtypes = [C.c_int]
+        L.acbm_profile_read.argtypes = [C.c_char_p, P(C.c_double), P(C.c_uint64)]
         _lib = L
     return _lib
 
@@ -249,6 +251,21 @@ class Batch:
         _check(lib().acbm_batch(self.table(), len(self.jobs), ws.data_ptr(), ws.numel(),
                                 _stream(stream)))
         return self.outs
+
+
+def profile_enable(on: bool):
+    _check(lib().acbm_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(lib().acbm_profile_reset())
+
+
+def profile_read(kernel: str) -> tuple[float, int]:
+    """(summed device ms, launches) of one kernel since the last reset."""
+    ms, n = C.c_double(), C.c_uint64()
+    _check(lib().acbm_profile_read(kernel.encode(), C.byref(ms), C.byref(n)))
+    return ms.value, n.value
 
 
 def to_numpy(res: torch.Tensor) -> np.ndarray:

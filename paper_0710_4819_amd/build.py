@@ -51,6 +51,26 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     return LIB
 
 
+PROBE_SRC = os.path.join(HERE, "probe", "probe_sad.hip")
+PROBE_BIN = os.path.join(HERE, "probe", "probe_sad")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The SAD-instruction probe (semantics and issue rate), a standalone
+    executable next to its source."""
+    tmp = PROBE_BIN + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", PROBE_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError(f"hipcc failed on the probe:\n{p.stderr}")
+    os.replace(tmp, PROBE_BIN)
+    return PROBE_BIN
+
+
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv)
+    build_probe(verbose="-v" in sys.argv)
     print(LIB)

@@ -96,22 +96,39 @@ int check_device() {
   return known_rc;
 }
 
-// Issue cost of one V_QSAD_PK_U16_U8 relative to a full-rate VALU op, used by
-// the planner (ACBM_QSAD_COST overrides it for tuning experiments).
+// Issue cost of one V_QSAD_PK_U16_U8 relative to a full-rate VALU op.  The
+// instruction probe measures 3.9 on gfx950 (quarter rate: 16 absolute
+// differences per lane every 4 clocks, the same byte rate as full-rate
+// V_SAD_U8).  ACBM_QSAD_COST overrides it for tuning experiments.
 static double qsad_cost() {
   static double c = [] {
     const char* e = std::getenv("ACBM_QSAD_COST");
-    return e ? std::atof(e) : 1.0;
+    return e ? std::atof(e) : 4.0;
   }();
   return c;
 }
 
+// Dynamic LDS a workgroup may use on the current device (less a margin for
+// the kernels' static LDS).
+int lds_limit() {
+  static int lim = [] {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        v <= 0)
+      v = 64 * 1024;
+    return v - 1024;
+  }();
+  return lim;
+}
+
 // Choose the candidate rows per lane R and the workgroup size.  Model per
-// wave-task, in CU clocks: VALU = R*M*N/4 QSADs; LDS = (R+M-1) window rows of
-// 2N bytes per lane at 128 B/clk; the slower of the two bounds the task.
-// With max_threads = 1024 every task gets its own thread (the full-search
-// kernel keeps all SADs of a block in registers); otherwise tasks loop over
-// a fixed group of max_threads.
+// wave-task, in CU clocks: VALU = R*M*N/4 QSADs at their issue cost; LDS =
+// (R+M-1) window rows of 2N bytes per lane at 128 B/clk; the slower of the
+// two bounds the task, plus a small epilogue term per row.  With
+// max_threads = 1024 every task gets its own thread (the full-search kernel
+// keeps all SADs of a block in registers); otherwise tasks loop over a fixed
+// group of max_threads.  R = 0 means no plan fits (window too large for LDS).
 SearchPlan plan_search(int N, int M, int p, int max_threads) {
   static const int Rs[] = {1, 2, 3, 4, 5, 6, 8, 11, 16};
   const char* force = std::getenv("ACBM_R");
@@ -135,7 +152,7 @@ SearchPlan plan_search(int N, int M, int p, int max_threads) {
       threads = max_threads;
       rounds = (tasks + threads - 1) / threads;
     }
-    if (lds > 64 * 1024) continue;
+    if (lds > lds_limit()) continue;
     const double valu = (double)R * M * (N / 4) * qsad_cost();
     const double ldsc = (double)(R + M - 1) * N;
     const double cost = (double)(threads / 64) * rounds * (std::max(valu, ldsc) + 8.0 * R);
@@ -144,7 +161,6 @@ SearchPlan plan_search(int N, int M, int p, int max_threads) {
       best = SearchPlan{R, threads, lds};
     }
   }
-  if (!best.R) best = SearchPlan{16, 1024, 0};
   return best;
 }
 

@@ -337,10 +337,15 @@ static int launch_search_nm(const KGeom& g, const SearchPlan& pl, const FramePtr
   dim3 grid(grid_x, npairs), block(pl.threads);
   switch (pl.R) {
 #define ACBM_CASE(RR)                                                                         \
-  case RR:                                                                                    \
+  case RR: {                                                                                  \
+    if (pl.lds_bytes > 64 * 1024)                                                             \
+      (void)hipFuncSetAttribute((const void*)k_search<N, M, RR, kTable>,                      \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, pl.lds_bytes);    \
+    ProfScope ps("search", st);                                                               \
     hipLaunchKernelGGL((k_search<N, M, RR, kTable>), grid, block, pl.lds_bytes, st, g, s, fr, \
                        table, recs, ovf, slack);                                              \
-    break;
+    break;                                                                                    \
+  }
     ACBM_R_LIST(ACBM_CASE)
 #undef ACBM_CASE
     default:
@@ -354,6 +359,7 @@ template <bool kTable>
 static int launch_search(const KGeom& g, const FramePtrs& fr, int npairs, uint32_t* table,
                          BlockRec* recs, uint16_t* ovf, uint32_t slack, hipStream_t st) {
   const SearchPlan pl = plan_search(g.bw, g.bh, g.p);
+  if (!pl.R) return fail(ACBM_E_UNSUPPORTED, "search window does not fit in LDS");
   if (g.bw == 16 && g.bh == 16)
     return launch_search_nm<16, 16, kTable>(g, pl, fr, npairs, table, recs, ovf, slack, st);
   if (g.bw == 16 && g.bh == 8)
@@ -413,6 +419,7 @@ int launch_fsbm(const KGeom& g, const acbm_params& prm, const uint8_t* const* fr
     uint16_t* o = ovf + (size_t)p0 * g.nb * (ovf_row_bytes(g) / 2);
     int rc = launch_search<false>(g, fr, n, nullptr, r, o, slack, st);
     if (rc) return rc;
+    ProfScope ps("resolve", st);
     hipLaunchKernelGGL(k_resolve, dim3(n), dim3(1024),
                        mv_in_lds ? (size_t)g.nb * sizeof(uint16_t) : 0, st, g, r, o,
                        out + (size_t)p0 * g.nb, prm.lambda,

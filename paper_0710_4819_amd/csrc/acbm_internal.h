@@ -56,6 +56,7 @@ constexpr uint32_t kStatusSpinTimeout = 1;
 
 size_t align256(size_t x);
 int rate_max(int p);  // 2 * se_bits(2p)
+int lds_limit();      // dynamic LDS bytes a workgroup may use on this device
 
 // Set the thread's error detail and return `code`.
 int fail(int code, const std::string& msg);
@@ -69,7 +70,22 @@ int check_device();
 
 SearchPlan plan_search(int N, int M, int p, int max_threads = 1024);
 
-// Launchers (acbm_kernels.hip).  All enqueue on `s` and return ACBM_* codes.
+// Brackets one kernel launch with timing events when profiling is on
+// (acbm_profile_enable); a no-op otherwise.
+class ProfScope {
+ public:
+  ProfScope(const char* name, hipStream_t st);
+  ~ProfScope();
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
+
+ private:
+  const char* name_;
+  hipStream_t st_;
+  void* a_ = nullptr;
+};
+
+// Launchers.  All enqueue on `s` and return ACBM_* codes.
 int launch_sad_table(const KGeom& g, const uint8_t* cur, const uint8_t* ref, uint32_t* table,
                      hipStream_t s);
 size_t fsbm_ws_bytes(const KGeom& g, uint32_t npairs);

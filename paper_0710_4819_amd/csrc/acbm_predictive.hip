@@ -435,10 +435,15 @@ static int launch_pred_nm(const PredArgs& a, const FramePtrs& fr, int R, size_t 
                           hipStream_t st) {
   switch (R) {
 #define ACBM_CASE(RR)                                                                    \
-  case RR:                                                                               \
+  case RR: {                                                                             \
+    if (lds > 64 * 1024)                                                                 \
+      (void)hipFuncSetAttribute((const void*)k_predictive<N, M, RR>,                     \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+    ProfScope ps("predictive", st);                                                      \
     hipLaunchKernelGGL((k_predictive<N, M, RR>), dim3(grid), dim3(kPredThreads), lds, st, \
                        a, fr);                                                           \
-    break;
+    break;                                                                               \
+  }
     ACBM_PRED_R_LIST(ACBM_CASE)
 #undef ACBM_CASE
     default:
@@ -464,6 +469,7 @@ int launch_predictive(const KGeom& g, const acbm_params& prm, int algo,
                       void* ws, size_t ws_bytes, acbm_block_result* out, hipStream_t st) {
   if (ws_bytes < predictive_ws_bytes(g, npairs)) return fail(ACBM_E_NOMEM, "workspace too small");
   const SearchPlan pl = plan_search(g.bw, g.bh, g.p, kPredThreads);
+  if (!pl.R) return fail(ACBM_E_UNSUPPORTED, "search window does not fit in LDS");
   for (uint32_t p0 = 0; p0 < npairs; p0 += kMaxPairsPerLaunch) {
     const int n = (int)std::min<uint32_t>(kMaxPairsPerLaunch, npairs - p0);
     PredArgs a{};
@@ -502,10 +508,13 @@ int launch_predictive(const KGeom& g, const acbm_params& prm, int algo,
     else if (g.bw == 8 && g.bh == 16) a.s = window_shape<8, 16>(g.p, pl.R);
     else a.s = window_shape<8, 8>(g.p, pl.R);
     const size_t lds = (size_t)((a.levels + 1 + 3) & ~3) * 4 + (size_t)a.s.rows * a.s.stride * 4;
-    if (lds > 64 * 1024) return fail(ACBM_E_UNSUPPORTED, "search window too large for LDS");
+    if (lds > (size_t)lds_limit()) return fail(ACBM_E_UNSUPPORTED, "search window too large for LDS");
 
     const int setup_grid = (int)std::min<size_t>(1024, ((size_t)n * g.nb + 255) / 256 + 1);
-    hipLaunchKernelGGL(k_pred_setup, dim3(setup_grid), dim3(256), 0, st, a);
+    {
+      ProfScope ps("setup", st);
+      hipLaunchKernelGGL(k_pred_setup, dim3(setup_grid), dim3(256), 0, st, a);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "launching the predictive setup");
 

@@ -250,8 +250,11 @@ bool acbm_server::try_start(const std::shared_ptr<Request>& r, Slot& s) {
       rc = launch_predictive(k, r->prm, (int)r->algo, frames, 1,
                              ss.has_field ? ss.field : nullptr, ws, wsb, out, s.st);
     if (!rc) {
-      hipLaunchKernelGGL(k_field_of, dim3((k.nb + 255) / 256), dim3(256), 0, s.st, out, k.nb,
-                         ss.field);
+      {
+        ProfScope ps("field", s.st);
+        hipLaunchKernelGGL(k_field_of, dim3((k.nb + 255) / 256), dim3(256), 0, s.st, out, k.nb,
+                           ss.field);
+      }
       e = hipGetLastError();
       if (e == hipSuccess) e = hipMemcpyAsync(s.pin_out, out, rb, hipMemcpyDeviceToHost, s.st);
       // the predictive kernel reports failed waits in the workspace header
