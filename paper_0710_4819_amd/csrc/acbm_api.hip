@@ -125,7 +125,7 @@ int lds_limit() {
 // Choose the candidate rows per lane R and the workgroup size.  Model per
 // wave-task, in CU clocks: VALU = R*M*N/4 QSADs at their issue cost; LDS =
 // (R+M-1) window rows of 2N bytes per lane at 128 B/clk; the slower of the
-// two bounds the task, plus a small epilogue term per row.  With
+// two bounds the task, plus a fixed cost per wave.  With
 // max_threads = 1024 every task gets its own thread (the full-search kernel
 // keeps all SADs of a block in registers); otherwise tasks loop over a fixed
 // group of max_threads.  R = 0 means no plan fits (window too large for LDS).
@@ -155,7 +155,11 @@ SearchPlan plan_search(int N, int M, int p, int max_threads) {
     if (lds > lds_limit()) continue;
     const double valu = (double)R * M * (N / 4) * qsad_cost();
     const double ldsc = (double)(R + M - 1) * N;
-    const double cost = (double)(threads / 64) * rounds * (std::max(valu, ldsc) + 8.0 * R);
+    // kWaveFixed: per-wave cost of the window load, the scalar load of the
+    // current block and the epilogue reductions, fitted to an R sweep of the
+    // 1920x1088 p = 32 search on MI355X (R = 5, 6 fastest; 2, 3 slowest).
+    constexpr double kWaveFixed = 2000.0;
+    const double cost = (double)(threads / 64) * rounds * (std::max(valu, ldsc) + kWaveFixed);
     if (cost < best_cost) {
       best_cost = cost;
       best = SearchPlan{R, threads, lds};

@@ -190,24 +190,54 @@ __device__ __forceinline__ void window_uv(uint32_t ras, int p, int* u, int* v) {
   *u = (int)(ras % (uint32_t)W) - p;
 }
 
-// Cheapest candidate of one block given its predictor.
-__device__ uint64_t block_argmin(const BlockRec* __restrict__ rec,
-                                 const uint16_t* __restrict__ row, int p, int px, int py,
-                                 uint32_t lam) {
+// Per-block state of the resolve: the decided vector packed in the low 16
+// bits (kMvUnset while open) and its SAD in the high 16 bits.
+constexpr uint32_t kOpen = 0xFFFF0000u | kMvUnset;
+__device__ __forceinline__ bool is_open(uint32_t w) { return (w & 0xFFFFu) == kMvUnset; }
+
+// Predictor of block b from the decided vectors; false if one of the three
+// neighbours it needs is still open.
+__device__ __forceinline__ bool median_pred(const uint32_t* st, int b, int r, int c, int bx,
+                                            int* px, int* py) {
+  uint32_t A = pack_mv(0, 0), B, C;
+  if (c > 0) {
+    A = st[b - 1];
+    if (is_open(A)) return false;
+  }
+  if (r == 0) {
+    B = A;
+    C = A;
+  } else {
+    B = st[b - bx];
+    C = (c == bx - 1) ? (uint32_t)pack_mv(0, 0) : st[b - bx + 1];
+    if (is_open(B) || is_open(C)) return false;
+  }
+  *px = med3(mv_x((uint16_t)A), mv_x((uint16_t)B), mv_x((uint16_t)C));
+  *py = med3(mv_y((uint16_t)A), mv_y((uint16_t)B), mv_y((uint16_t)C));
+  return true;
+}
+
+// Cheapest candidate of one block, computed by a whole wave: the 128-byte
+// record is read with one dword per lane, each listed candidate is priced by
+// its own lane; an overflowed block's row is strided over the lanes.
+__device__ __forceinline__ uint64_t wave_block_argmin(const BlockRec* __restrict__ rec,
+                                                      const uint16_t* __restrict__ row, int p,
+                                                      int px, int py, uint32_t lam) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t w = lane < 32 ? reinterpret_cast<const uint32_t*>(rec)[lane] : 0u;
+  const uint32_t n = (uint32_t)__shfl((int)w, 1, 64);  // rec->count
   uint64_t best = ~0ull;
-  const uint32_t n = rec->count;
   if (n <= (uint32_t)kShort) {
-    for (uint32_t k = 0; k < n; ++k) {
-      const uint32_t e = rec->e[k];
+    const int k = lane - 4;  // e[k] is dword 4 + k of the record
+    if (k >= 0 && k < (int)n) {
       int u, v;
-      window_uv(e & 0xFFFFu, p, &u, &v);
-      const uint32_t j = (e >> 16) + lam * (se_bits(u - px) + se_bits(v - py));
-      const uint64_t key = make_key(j, u, v, p);
-      best = key < best ? key : best;
+      window_uv(w & 0xFFFFu, p, &u, &v);
+      const uint32_t j = (w >> 16) + lam * (se_bits(u - px) + se_bits(v - py));
+      best = make_key(j, u, v, p);
     }
   } else {
-    const int W = 2 * p + 1;
-    for (int ras = 0; ras < W * W; ++ras) {
+    const int WW = (2 * p + 1) * (2 * p + 1);
+    for (int ras = lane; ras < WW; ras += 64) {
       const uint32_t sad = row[ras];
       if (sad == 0xFFFFu) continue;
       int u, v;
@@ -217,84 +247,70 @@ __device__ uint64_t block_argmin(const BlockRec* __restrict__ rec,
       best = key < best ? key : best;
     }
   }
-  return best;
+  return wave_min_u64(best);
 }
 
-__device__ __forceinline__ uint32_t sad_of(const BlockRec* __restrict__ rec,
-                                           const uint16_t* __restrict__ row, uint32_t ras) {
-  const uint32_t n = rec->count;
-  if (n > (uint32_t)kShort) return row[ras];
-  for (uint32_t k = 0; k < n; ++k)
-    if ((rec->e[k] & 0xFFFFu) == ras) return rec->e[k] >> 16;
-  return 0xFFFFFFFFu;  // unreachable: the winner is always in the list
-}
-
-// Predictor of block b from the packed vectors in `mvs`; false if one of the
-// neighbours it needs is not decided yet.
-__device__ __forceinline__ bool median_pred(const uint16_t* mvs, int b, int r, int c, int bx,
-                                            int* px, int* py) {
-  uint16_t A = pack_mv(0, 0), B, C;
-  if (c > 0) {
-    A = mvs[b - 1];
-    if (A == kMvUnset) return false;
-  }
-  if (r == 0) {
-    B = A;
-    C = A;
-  } else {
-    B = mvs[b - bx];
-    C = (c == bx - 1) ? pack_mv(0, 0) : mvs[b - bx + 1];
-    if (B == kMvUnset || C == kMvUnset) return false;
-  }
-  *px = med3(mv_x(A), mv_x(B), mv_x(C));
-  *py = med3(mv_y(A), mv_y(B), mv_y(C));
-  return true;
-}
-
-// The decided vectors live in LDS when they fit (mv_global == nullptr), else
-// in a workspace array; either way only this workgroup touches them.
+// One workgroup per frame pair.  The state lives in LDS when it fits
+// (st_global == nullptr), else in a workspace array; either way only this
+// workgroup touches it.
 __global__ void __launch_bounds__(1024)
 k_resolve(const KGeom g, const BlockRec* __restrict__ recs, const uint16_t* __restrict__ ovf,
-          acbm_block_result* __restrict__ out, uint32_t lam, uint16_t* mv_global) {
-  extern __shared__ uint16_t mv_lds[];
+          acbm_block_result* __restrict__ out, uint32_t lam, uint32_t* st_global) {
+  extern __shared__ uint32_t st_lds[];
   __shared__ int pending;
   const int pair = blockIdx.x;
   const int p = g.p, W = 2 * p + 1, nb = g.nb, bx = g.bx;
-  uint16_t* mvs = mv_global ? mv_global + (size_t)pair * nb : mv_lds;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  uint32_t* st = st_global ? st_global + (size_t)pair * nb : st_lds;
   recs += (size_t)pair * nb;
   ovf += (size_t)pair * nb * (size_t)(W * W);
   out += (size_t)pair * nb;
 
   // blocks with a single possible winner are decided without a predictor
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-    uint16_t m = kMvUnset;
+    uint32_t w = kOpen;
     if (recs[b].count == 1) {
+      const uint32_t e = recs[b].e[0];
       int u, v;
-      window_uv(recs[b].e[0] & 0xFFFFu, p, &u, &v);
-      m = pack_mv(u, v);
+      window_uv(e & 0xFFFFu, p, &u, &v);
+      w = (e & 0xFFFF0000u) | pack_mv(u, v);
     }
-    mvs[b] = m;
+    st[b] = w;
   }
   __syncthreads();
 
-  // sweep until every block is decided; each sweep decides at least the
-  // first undecided block in raster order, whose neighbours all precede it,
-  // so nb sweeps always suffice
+  // Sweep until every block is decided.  Each sweep decides at least the
+  // first open block in raster order (its neighbours all precede it), so nb
+  // sweeps always suffice.  Lanes find the ready blocks of a 64-block chunk;
+  // the wave then prices each of them together.
   for (int sweep = 0; sweep <= nb; ++sweep) {
     if (threadIdx.x == 0) pending = 0;
     __syncthreads();
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-      if (mvs[b] != kMvUnset) continue;
-      const int r = b / bx, c = b - r * bx;
-      int px, py;
-      if (!median_pred(mvs, b, r, c, bx, &px, &py)) {
-        pending = 1;
-        continue;
+    for (int base = wave * 64; base < nb; base += nwaves * 64) {
+      const int b = base + lane;
+      int px = 0, py = 0;
+      bool ready = false;
+      if (b < nb && is_open(st[b])) {
+        const int r = b / bx, c = b - r * bx;
+        ready = median_pred(st, b, r, c, bx, &px, &py);
+        if (!ready) pending = 1;
       }
-      const uint64_t key = block_argmin(recs + b, ovf + (size_t)b * (W * W), p, px, py, lam);
-      int u = 0, v = 0;
-      if (key != ~0ull) window_uv((uint32_t)(key & 0xFFFFu), p, &u, &v);
-      mvs[b] = pack_mv(u, v);
+      uint64_t mask = __ballot(ready);
+      while (mask) {
+        const int k = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const int bb = base + k;
+        const int qx = __shfl(px, k, 64), qy = __shfl(py, k, 64);
+        const uint64_t key =
+            wave_block_argmin(recs + bb, ovf + (size_t)bb * (W * W), p, qx, qy, lam);
+        int u = 0, v = 0;
+        uint32_t sad = 0;
+        if (key != ~0ull) {
+          window_uv((uint32_t)(key & 0xFFFFu), p, &u, &v);
+          sad = (uint32_t)(key >> 32) - lam * (se_bits(u - qx) + se_bits(v - qy));
+        }
+        if (lane == 0) st[bb] = (sad << 16) | pack_mv(u, v);
+      }
     }
     __syncthreads();
     const int again = pending;
@@ -304,11 +320,11 @@ k_resolve(const KGeom g, const BlockRec* __restrict__ recs, const uint16_t* __re
 
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
     const int r = b / bx, c = b - r * bx;
-    int px, py;
-    median_pred(mvs, b, r, c, bx, &px, &py);
-    const int u = mv_x(mvs[b]), v = mv_y(mvs[b]);
-    const uint32_t ras = (uint32_t)((v + p) * W + (u + p));
-    const uint32_t sad = sad_of(recs + b, ovf + (size_t)b * (W * W), ras);
+    int px = 0, py = 0;
+    median_pred(st, b, r, c, bx, &px, &py);
+    const uint32_t w = st[b];
+    const int u = mv_x((uint16_t)w), v = mv_y((uint16_t)w);
+    const uint32_t sad = w >> 16;
     const uint32_t rate = se_bits(u - px) + se_bits(v - py);
     acbm_block_result res;
     res.mv.x = (int16_t)u;
@@ -384,12 +400,12 @@ static size_t ovf_row_bytes(const KGeom& g) {
   return W * W * sizeof(uint16_t);
 }
 
-// Vectors of the resolve kernel stay in LDS up to this many bytes.
+// State of the resolve kernel stays in LDS up to this many bytes.
 constexpr size_t kResolveLdsMax = 48 * 1024;
 
 size_t fsbm_ws_bytes(const KGeom& g, uint32_t npairs) {
-  const size_t mv_bytes = (size_t)g.nb * sizeof(uint16_t) > kResolveLdsMax
-                              ? align256((size_t)npairs * g.nb * sizeof(uint16_t))
+  const size_t mv_bytes = (size_t)g.nb * sizeof(uint32_t) > kResolveLdsMax
+                              ? align256((size_t)npairs * g.nb * sizeof(uint32_t))
                               : 0;
   return align256(sizeof(WsHeader)) + align256((size_t)npairs * g.nb * sizeof(BlockRec)) +
          align256((size_t)npairs * g.nb * ovf_row_bytes(g)) + mv_bytes;
@@ -403,9 +419,9 @@ int launch_fsbm(const KGeom& g, const acbm_params& prm, const uint8_t* const* fr
   BlockRec* recs = reinterpret_cast<BlockRec*>(base + align256(sizeof(WsHeader)));
   uint16_t* ovf = reinterpret_cast<uint16_t*>(
       base + align256(sizeof(WsHeader)) + align256((size_t)npairs * g.nb * sizeof(BlockRec)));
-  const bool mv_in_lds = (size_t)g.nb * sizeof(uint16_t) <= kResolveLdsMax;
-  uint16_t* mv_ws = mv_in_lds ? nullptr
-                              : reinterpret_cast<uint16_t*>(
+  const bool mv_in_lds = (size_t)g.nb * sizeof(uint32_t) <= kResolveLdsMax;
+  uint32_t* mv_ws = mv_in_lds ? nullptr
+                              : reinterpret_cast<uint32_t*>(
                                     base + align256(sizeof(WsHeader)) +
                                     align256((size_t)npairs * g.nb * sizeof(BlockRec)) +
                                     align256((size_t)npairs * g.nb * ovf_row_bytes(g)));
@@ -421,7 +437,7 @@ int launch_fsbm(const KGeom& g, const acbm_params& prm, const uint8_t* const* fr
     if (rc) return rc;
     ProfScope ps("resolve", st);
     hipLaunchKernelGGL(k_resolve, dim3(n), dim3(1024),
-                       mv_in_lds ? (size_t)g.nb * sizeof(uint16_t) : 0, st, g, r, o,
+                       mv_in_lds ? (size_t)g.nb * sizeof(uint32_t) : 0, st, g, r, o,
                        out + (size_t)p0 * g.nb, prm.lambda,
                        mv_in_lds ? nullptr : mv_ws + (size_t)p0 * g.nb);
     hipError_t e = hipGetLastError();
