@@ -43,25 +43,63 @@ __device__ __forceinline__ uint64_t make_key(uint32_t j, int u, int v, int p) {
 }
 
 // ---------------------------------------------------------------------------
-// Reductions over a wave64 and over a workgroup.
+// Reductions over a wave64 (the ROCm device library's DPP reductions; every
+// lane of the wave must be active) and over a workgroup.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
+}  // namespace acbm
+extern "C" __device__ uint64_t __ockl_wfred_min_u64(uint64_t);
+extern "C" __device__ uint32_t __ockl_wfred_min_u32(uint32_t);
+extern "C" __device__ uint32_t __ockl_wfred_add_u32(uint32_t);
+namespace acbm {
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) { return __ockl_wfred_min_u64(x); }
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) { return __ockl_wfred_min_u32(x); }
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) { return __ockl_wfred_add_u32(x); }
+
+// Minimum of the four 16-bit lanes of each of R accumulators.
+typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
+template <int R>
+__device__ __forceinline__ uint32_t min_u16_lanes(const uint64_t (&acc)[R]) {
+  ushort2_t m = __builtin_bit_cast(ushort2_t, (uint32_t)acc[0]);
+  m = __builtin_elementwise_min(m, __builtin_bit_cast(ushort2_t, (uint32_t)(acc[0] >> 32)));
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    uint64_t y = __shfl_xor(x, o, 64);
-    x = y < x ? y : x;
+  for (int rr = 1; rr < R; ++rr) {
+    m = __builtin_elementwise_min(m, __builtin_bit_cast(ushort2_t, (uint32_t)acc[rr]));
+    m = __builtin_elementwise_min(m, __builtin_bit_cast(ushort2_t, (uint32_t)(acc[rr] >> 32)));
   }
-  return x;
+  return min((uint32_t)m.x, (uint32_t)m.y);
 }
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) x = min(x, (uint32_t)__shfl_xor((int)x, o, 64));
-  return x;
+
+// Valid candidate range of a block: u in [u_min, u_max], v in [v_min, v_max]
+// (|u|, |v| <= p and the displaced block inside the frame).
+struct ValidBox {
+  int u_min, u_max, v_min, v_max;
+};
+__device__ __forceinline__ ValidBox valid_box(int p, int x0, int y0, int N, int M, int width,
+                                              int height) {
+  ValidBox b;
+  b.u_min = max(-p, -x0);
+  b.u_max = min(p, width - N - x0);
+  b.v_min = max(-p, -y0);
+  b.v_max = min(p, height - M - y0);
+  return b;
 }
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+
+// Sets the 16-bit lane of every invalid candidate of a task to 0xFFFF (no
+// valid SAD reaches it: 255 * 256 = 65280).  Lane i of acc[rr] is candidate
+// (u0 + i, v0 + rr).
+template <int R>
+__device__ __forceinline__ void mask_invalid(uint64_t (&acc)[R], const ValidBox& bx, int u0,
+                                             int v0) {
+  uint64_t colmask = 0;
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) x += (uint32_t)__shfl_xor((int)x, o, 64);
-  return x;
+  for (int i = 0; i < 4; ++i)
+    if (u0 + i < bx.u_min || u0 + i > bx.u_max) colmask |= 0xFFFFull << (16 * i);
+#pragma unroll
+  for (int rr = 0; rr < R; ++rr) {
+    const int v = v0 + rr;
+    acc[rr] |= (v < bx.v_min || v > bx.v_max) ? ~0ull : colmask;
+  }
 }
 
 // Workgroup minimum; `scratch` holds one slot per wave.  Every thread gets

@@ -95,6 +95,11 @@ k_search(const KGeom g, const WindowShape s, const FramePtrs fr, uint32_t* __res
   if (active) task_sads<N, M, R>(win, s.stride, q, gi, cb, acc);
 
   const int u0 = s.u_lo + 4 * q, v0 = -p + R * gi;
+  // invalid candidates (outside the frame, or the padding of the quads and
+  // row groups beyond +-p) read as 0xFFFF from here on
+  const ValidBox vbox = valid_box(p, x0, y0, N, M, g.width, g.height);
+  if (active) mask_invalid<R>(acc, vbox, u0, v0);
+
   if (kTable) {
     if (!active) return;
     uint32_t* out = table + (size_t)b * W * W;
@@ -107,54 +112,36 @@ k_search(const KGeom g, const WindowShape s, const FramePtrs fr, uint32_t* __res
         const int u = u0 + i;
         if (u < -p || u > p) continue;
         const uint32_t sad = (uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu;
-        out[(v + p) * W + (u + p)] =
-            cand_valid(u, v, p, x0, y0, N, M, g.width, g.height) ? sad : 0xFFFFFFFFu;
+        out[(v + p) * W + (u + p)] = sad == 0xFFFFu ? 0xFFFFFFFFu : sad;
       }
     }
     return;
   }
 
   // ---- FSBM: SAD minimum and the candidates that can still win ----------
-  uint32_t lmin = 0xFFFFFFFFu;
-  if (active) {
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int u = u0 + i, v = v0 + rr;
-        if (cand_valid(u, v, p, x0, y0, N, M, g.width, g.height))
-          lmin = min(lmin, (uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu);
-      }
-  }
+  const uint32_t lmin = active ? min_u16_lanes<R>(acc) : 0xFFFFu;
   const uint32_t smin = (uint32_t)group_min_u64(lmin, red);
-  const uint64_t thr = (uint64_t)smin + slack;
+  const uint32_t thr = (uint32_t)min<uint64_t>((uint64_t)smin + slack, 0xFFFEu);
 
   BlockRec* rec = recs + ((size_t)pair * g.nb + b);
-  if (active) {
+  if (active && lmin <= thr) {  // rare: this lane holds a possible winner
     uint32_t mine = 0;
 #pragma unroll
     for (int rr = 0; rr < R; ++rr)
 #pragma unroll
+      for (int i = 0; i < 4; ++i) mine += ((uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu) <= thr;
+    uint32_t slot = atomicAdd(&n_keep, mine);
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr)
+#pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int u = u0 + i, v = v0 + rr;
         const uint32_t sad = (uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu;
-        if (cand_valid(u, v, p, x0, y0, N, M, g.width, g.height) && sad <= thr) ++mine;
-      }
-    if (mine) {
-      uint32_t slot = atomicAdd(&n_keep, mine);
-#pragma unroll
-      for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int u = u0 + i, v = v0 + rr;
-          const uint32_t sad = (uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu;
-          if (cand_valid(u, v, p, x0, y0, N, M, g.width, g.height) && sad <= thr) {
-            if (slot < (uint32_t)kShort)
-              rec->e[slot] = (sad << 16) | (uint32_t)((v + p) * W + (u + p));
-            ++slot;
-          }
+        if (sad <= thr) {
+          if (slot < (uint32_t)kShort)
+            rec->e[slot] = (sad << 16) | (uint32_t)((v0 + rr + p) * W + (u0 + i + p));
+          ++slot;
         }
-    }
+      }
   }
   __syncthreads();
   const uint32_t total = n_keep;
@@ -168,9 +155,7 @@ k_search(const KGeom g, const WindowShape s, const FramePtrs fr, uint32_t* __res
       for (int i = 0; i < 4; ++i) {
         const int u = u0 + i;
         if (u < -p || u > p) continue;
-        const uint32_t sad = (uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu;
-        row[(v + p) * W + (u + p)] =
-            cand_valid(u, v, p, x0, y0, N, M, g.width, g.height) ? (uint16_t)sad : (uint16_t)0xFFFF;
+        row[(v + p) * W + (u + p)] = (uint16_t)(acc[rr] >> (16 * i));
       }
     }
   }
