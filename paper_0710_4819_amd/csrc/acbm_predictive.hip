@@ -11,10 +11,9 @@
 //    read (r-1 of pair t; r-1, r, r+1 of pair t-1) have smaller levels.  A
 //    workgroup (row walker) takes one row ticket at a time, in level order,
 //    from one counter and walks the row left to right.  The smallest
-//    unfinished ticket always
-//    has every row it reads finished, so the kernel cannot deadlock however
-//    many workgroups are resident; rows of many frames run at once (pair t
-//    starts while pair t-1 is still running).  A row walker has 128 threads
+//    unfinished ticket always has every row it reads finished, so the kernel
+//    cannot deadlock however many workgroups are resident; rows of many
+//    frames run at once (pair t starts while pair t-1 is still running).  A row walker has 128 threads
 //    by default: on the 1920x1088 p = 32 sequence that measured faster than
 //    64 (longer critical searches) and 256 (fewer rows in flight).
 //  * Publication.  A finished block stores its vector together with a ready
