@@ -49,6 +49,17 @@ class CParams(C.Structure):
                 ("beta", C.c_uint32), ("gamma_num", C.c_uint32), ("gamma_den", C.c_uint32)]
 
 
+class ServeCfg(C.Structure):
+    _fields_ = [("pool_bytes", C.c_size_t), ("max_streams", C.c_uint32),
+                ("max_inflight", C.c_uint32), ("queue_depth", C.c_uint32)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [("completed", C.c_uint64), ("rejected", C.c_uint64), ("p50_us", C.c_double),
+                ("p99_us", C.c_double), ("mean_us", C.c_double), ("throughput_rps", C.c_double),
+                ("gpu_busy_frac", C.c_double)]
+
+
 class Job(C.Structure):
     _fields_ = [("geom", Geom), ("params", CParams), ("algo", C.c_uint32),
                 ("nframes", C.c_uint32), ("frames", C.POINTER(C.c_void_p)),
@@ -106,6 +117,12 @@ def lib():
         L.acbm_acbm_frame.argtypes = [P(Geom), P(CParams), vp, vp, vp, vp, vp, sz, vp]
         L.acbm_batch_workspace_size.argtypes = [P(Job), sz, P(sz)]
         L.acbm_batch.argtypes = [P(Job), sz, vp, sz, vp]
+        L.acbm_serve.argtypes = [P(ServeCfg), P(vp)]
+        L.acbm_serve_submit.argtypes = [vp, C.c_uint32, vp, P(Geom), P(CParams), C.c_uint32,
+                                        P(C.c_uint64)]
+        L.acbm_serve_wait.argtypes = [vp, C.c_uint64, vp, C.c_int64]
+        L.acbm_serve_stats_get.argtypes = [vp, P(ServeStats)]
+        L.acbm_serve_close.argtypes = [vp]
         L.acbm_profile_enable.argtypes = [C.c_int]
         L.acbm_profile_read.argtypes = [C.c_char_p, P(C.c_double), P(C.c_uint64)]
         _lib = L
@@ -251,6 +268,49 @@ class Batch:
         _check(lib().acbm_batch(self.table(), len(self.jobs), ws.data_ptr(), ws.numel(),
                                 _stream(stream)))
         return self.outs
+
+
+class Server:
+    """Frame-pair motion estimation requests over device-resident streams
+    (acbm_serve).  Frames are host numpy arrays [height, pitch] uint8."""
+
+    def __init__(self, pool_bytes=4 << 30, max_streams=32, max_inflight=4, queue_depth=256):
+        self.h = C.c_void_p()
+        cfg = ServeCfg(pool_bytes, max_streams, max_inflight, queue_depth)
+        _check(lib().acbm_serve(C.byref(cfg), C.byref(self.h)))
+        self.geoms = {}
+
+    def submit(self, stream_id: int, frame: np.ndarray, block_w: int, block_h: int, p: int,
+               params: Params, algo: int, width: int | None = None) -> int:
+        frame = np.ascontiguousarray(frame, dtype=np.uint8)
+        g = Geom(frame.shape[1] if width is None else width, frame.shape[0], frame.shape[1],
+                 block_w, block_h, p)
+        t = C.c_uint64()
+        rc = lib().acbm_serve_submit(self.h, stream_id, frame.ctypes.data, C.byref(g),
+                                     C.byref(params.c()), algo, C.byref(t))
+        _check(rc)
+        self.geoms[t.value] = g
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> np.ndarray | None:
+        """Results of a ticket as a structured array [by, bx] (None for a
+        stream's first frame, which only becomes its reference)."""
+        g = self.geoms.pop(ticket)
+        by, bx = g.height // g.block_h, g.width // g.block_w
+        out = np.zeros((by, bx), dtype=RESULT_DTYPE)
+        out["mode"] = 0xFFFFFFFF
+        _check(lib().acbm_serve_wait(self.h, ticket, out.ctypes.data, timeout_us))
+        return None if (out["mode"] == 0xFFFFFFFF).all() else out
+
+    def stats(self) -> dict:
+        st = ServeStats()
+        _check(lib().acbm_serve_stats_get(self.h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServeStats._fields_}
+
+    def close(self):
+        if self.h:
+            _check(lib().acbm_serve_close(self.h))
+            self.h = C.c_void_p()
 
 
 def profile_enable(on: bool):

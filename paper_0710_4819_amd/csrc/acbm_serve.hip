@@ -398,10 +398,12 @@ int acbm_serve_submit(acbm_server* s, uint32_t stream_id, const uint8_t* host_fr
   }
   // a stream keeps one geometry; its first frame only becomes the reference
   StreamState& ss = s->streams[stream_id];
-  bool known = ss.open;
-  for (const auto& q : s->queue) known |= q->stream == stream_id;
-  if (ss.open && std::memcmp(&ss.g, g, sizeof(*g)) != 0)
+  const acbm_geom* first = ss.open ? &ss.g : nullptr;
+  for (const auto& q : s->queue)
+    if (!first && q->stream == stream_id) first = &q->g;
+  if (first && std::memcmp(first, g, sizeof(*g)) != 0)
     return fail(ACBM_E_SHAPE, "geometry differs from the stream's first frame");
+  const bool known = first != nullptr;
   auto r = std::make_shared<Request>();
   r->ticket = s->next_ticket++;
   r->stream = stream_id;
