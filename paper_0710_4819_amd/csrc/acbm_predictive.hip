@@ -206,6 +206,20 @@ __device__ __forceinline__ void park_columns(uint32_t* __restrict__ ring, const 
   }
 }
 
+// Sum over aligned groups of G = 8 or 16 lanes, left in every lane of the
+// group: swaps within quads, then the mirror within 8 lanes, then (G = 16)
+// the mirror within 16 lanes.
+template <int G>
+__device__ __forceinline__ uint32_t group_sum(uint32_t x) {
+  static_assert(G == 8 || G == 16, "row sums of 8 or 16 lanes");
+  x += (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+  x += (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+  x += (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  if constexpr (G == 16)
+    x += (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x140, 0xF, 0xF, false);  // row_mirror
+  return x;
+}
+
 // ---------------------------------------------------------------------------
 // PBM: SADs of the 3 x 4 neighbourhood (u-1..u+2) x (v-1..v+1) of every
 // predictor candidate.  nbr[ci][dv] holds four u16 SADs, columns u-1+i in
@@ -250,20 +264,41 @@ __device__ __forceinline__ void pbm_neighbourhoods(const uint32_t* __restrict__ 
         }
       }
     }
-    // sum over the block rows; a 16-bit lane never carries (SAD <= 255*N*M)
+    // Sum over the block rows.  A 16-bit lane never carries (SAD <= 255*N*M),
+    // so the two dwords add independently.
 #pragma unroll
-    for (int o = M / 2; o >= 1; o >>= 1)
-#pragma unroll
-      for (int dv = 0; dv < 3; ++dv) {
-        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)acc[dv], o, 64);
-        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(acc[dv] >> 32), o, 64);
-        acc[dv] += ((uint64_t)hi << 32) | lo;
-      }
+    for (int dv = 0; dv < 3; ++dv)
+      acc[dv] = ((uint64_t)group_sum<M>((uint32_t)(acc[dv] >> 32)) << 32) |
+                group_sum<M>((uint32_t)acc[dv]);
     if (ci < np && j == 0) {
 #pragma unroll
       for (int dv = 0; dv < 3; ++dv) nbr[ci][dv] = acc[dv];
     }
   }
+}
+
+// Minimum over lanes 0..15 of a 64-bit key, left in each of those lanes
+// (same DPP pattern as group_sum).
+__device__ __forceinline__ uint64_t row_min_u64(uint64_t x) {
+#define ACBM_ROW_MIN_STEP(CTRL)                                                       \
+  {                                                                                   \
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)x, CTRL, 0xF, 0xF, false); \
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(x >> 32), CTRL, 0xF, 0xF, false); \
+    const uint64_t y = ((uint64_t)hi << 32) | lo;                                     \
+    x = y < x ? y : x;                                                                \
+  }
+  ACBM_ROW_MIN_STEP(0xB1)
+  ACBM_ROW_MIN_STEP(0x4E)
+  ACBM_ROW_MIN_STEP(0x141)
+  ACBM_ROW_MIN_STEP(0x140)
+#undef ACBM_ROW_MIN_STEP
+  return x;
+}
+
+// Lane 0's value, in every lane (wave-uniform).
+__device__ __forceinline__ uint64_t lane0_u64(uint64_t x) {
+  return ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(x >> 32), 0) << 32) |
+         __builtin_amdgcn_readlane((uint32_t)x, 0);
 }
 
 __device__ __forceinline__ uint32_t field16(uint64_t x, int i) {
@@ -394,7 +429,7 @@ k_predictive(const PredArgs a) {
   __shared__ uint32_t curd[2][D];
   __shared__ int16_t cu[kMaxCands], cv[kMaxCands];
   __shared__ uint64_t nbr[kMaxCands][3];
-  __shared__ int sh_row, sh_abort, sh_np, sh_px, sh_py, sh_crit;
+  __shared__ int sh_row, sh_abort, sh_np, sh_px, sh_py;
   __shared__ uint32_t sh_intra;
   __shared__ uint16_t sh_left;
 
@@ -503,7 +538,7 @@ k_predictive(const PredArgs a) {
         const uint32_t tagged = ok ? (uint32_t)val : 0xFFFFFFFFu;
         bool dup = false;
 #pragma unroll
-        for (int q = 0; q < 13; ++q) dup |= q < lane && __builtin_amdgcn_readlane(tagged, q) == tagged;
+        for (int q = 0; q < 13; ++q) dup |= (q < lane) & (__builtin_amdgcn_readlane(tagged, q) == tagged);
         const bool keep = ok && !dup;
         const uint64_t mask = __ballot(keep);
         if (keep) {
@@ -547,24 +582,32 @@ k_predictive(const PredArgs a) {
       const int px = sh_px, py = sh_py;
       const int np = sh_np;
 
-      // ---- B: predictor neighbourhoods (all waves) ------------------------
+      // ---- B: predictor neighbourhoods (all waves).  The predictor state is
+      //         copied to registers before the barrier: once past it, wave 0
+      //         may already rewrite it for the next block. ----------------
+      const uint32_t intra = sh_intra;
+      int cand_u = 0, cand_v = 0;
+      if (lane < np) {
+        cand_u = cu[lane];
+        cand_v = cv[lane];
+      }
       pbm_neighbourhoods<N, M, NT>(ring, w, cb0, cd, cu, cv, np, nbr);
       __syncthreads();
 
-      // ---- C: PBM steps 2 and 3, ACBM decision (wave 0) -------------------
-      if (wave == 0) {
-        int u = 0, v = 0;
+      // ---- C: PBM steps 2 and 3, ACBM decision (every wave, redundantly, so
+      //         that no barrier is needed to share it) -----------------------
+      int crit_n = 0;  // candidates PBM evaluated, if the block is critical
+      {
+        const int u = cand_u, v = cand_v;
         uint64_t key = ~0ull;
         if (lane < np) {
-          u = cu[lane];
-          v = cv[lane];
           const uint32_t sad = field16(nbr[lane][1], 1);
           key = make_key(sad + a.lam * (se_bits(u - px) + se_bits(v - py)), u, v, p);
         }
-        const uint64_t k2 = wave_min_u64(key);
+        // at most 14 predictors and 8 neighbours: minima over lanes 0..15
+        const uint64_t k2 = lane0_u64(row_min_u64(key));
         const int bi = __builtin_ctzll(__ballot(lane < np && key == k2));
-        const int ras = (int)(k2 & 0xFFFFu);
-        const int bu = ras % W - p, bv = ras / W - p;
+        const int bu = __builtin_amdgcn_readlane(u, bi), bv = __builtin_amdgcn_readlane(v, bi);
         // the valid 8-neighbours of the step-2 winner that are not predictors
         const int dd = lane < 4 ? lane : lane + 1;  // skip the centre
         const int du = dd % 3 - 1, dv = dd / 3 - 1;
@@ -578,54 +621,61 @@ k_predictive(const PredArgs a) {
           const uint32_t sad = field16(nbr[bi][dv + 1], du + 1);
           key3 = make_key(sad + a.lam * (se_bits(un - px) + se_bits(vn - py)), un, vn, p);
         }
-        const uint64_t k3 = wave_min_u64(key3);
-        const uint64_t best = k3 < k2 ? k3 : k2;
+        const uint64_t k3 = lane0_u64(row_min_u64(key3));
         const uint32_t n = (uint32_t)(np + __builtin_popcountll(__ballot(add)));
-        const int bras = (int)(best & 0xFFFFu);
-        const int fu = bras % W - p, fv = bras / W - p;
+        int fu = bu, fv = bv;
+        uint64_t best = k2;
+        if (k3 < k2) {
+          const int wl = __builtin_ctzll(__ballot(add && key3 == k3));
+          fu = __builtin_amdgcn_readlane(un, wl);
+          fv = __builtin_amdgcn_readlane(vn, wl);
+          best = k3;
+        }
         const uint32_t rate = se_bits(fu - px) + se_bits(fv - py);
         const uint32_t jv = (uint32_t)(best >> 32);
         const uint32_t sad = jv - a.lam * rate;
         int mode = ACBM_MODE_PBM;
         if (a.algo == ACBM_ALGO_ACBM) {
-          const uint64_t nm = (uint64_t)(N * M), ix = sh_intra;
+          const uint64_t nm = (uint64_t)(N * M), ix = intra;
           if (ix + nm * sad < a.c1_rhs) mode = ACBM_MODE_PBM_C1;
           else if ((uint64_t)a.gamma_den * nm * sad < (uint64_t)a.gamma_num * ix) mode = ACBM_MODE_PBM_C2;
           else mode = ACBM_MODE_CRITICAL;
         }
-        if (lane == 0) {
-          sh_crit = mode == ACBM_MODE_CRITICAL ? (int)n : 0;
-          if (mode != ACBM_MODE_CRITICAL) {
-            write_result(a.out + (size_t)t * nb + b, words + b, fu, fv, jv, rate, a.lam, n,
-                         (uint32_t)mode, sh_intra);
-            sh_left = pack_mv(fu, fv);
-          }
+        if (mode == ACBM_MODE_CRITICAL) {
+          crit_n = (int)n;
+        } else if (threadIdx.x == 0) {
+          write_result(a.out + (size_t)t * nb + b, words + b, fu, fv, jv, rate, a.lam, n,
+                       (uint32_t)mode, intra);
+          sh_left = pack_mv(fu, fv);
         }
       }
-      __syncthreads();
 
       // ---- D: critical block: full search with the same predictor ---------
-      if (sh_crit) {
+      if (crit_n) {  // uniform: every wave took the same decision
         const ValidBox vbox = valid_box(p, x0, y0, N, M, g.width, g.height);
+        __builtin_amdgcn_s_setprio(3);  // the full search is on this row's critical path
         const uint64_t best = critical_search<N, M, R>(ring, w, cb0, cd, vbox, px, py, a.lam, red);
+        __builtin_amdgcn_s_setprio(0);
         if (threadIdx.x == 0) {
           const int ras = (int)(best & 0xFFFFu);
           const int u = ras % W - p, v = ras / W - p;
           const uint32_t rate = se_bits(u - px) + se_bits(v - py);
-          const uint32_t cands = (uint32_t)sh_crit + valid_count(p, x0, y0, N, M, g.width, g.height);
+          const uint32_t cands = (uint32_t)crit_n + valid_count(p, x0, y0, N, M, g.width, g.height);
           write_result(a.out + (size_t)t * nb + b, words + b, u, v, (uint32_t)(best >> 32), rate,
-                       a.lam, cands, ACBM_MODE_CRITICAL, sh_intra);
+                       a.lam, cands, ACBM_MODE_CRITICAL, intra);
           sh_left = pack_mv(u, v);
         }
       }
 
-      // ---- E: park what block c+1 adds -------------------------------------
+      // ---- E: park what block c+1 adds.  No barrier: the next block's first
+      //         barrier orders these writes before any read of them, and
+      //         wave 0 meanwhile only touches the predictor state. -----------
       if (more && wave > 0) {
         park_columns<N>(ring, nxt, w, ref, g, y0, cb0 + w.s.dws, f, nf);
         if (f < D) curd[cb ^ 1][f] = nxt_cur;
       }
-      __syncthreads();
     }
+    __syncthreads();  // the row's last block is done before the ring is refilled
   }
 }
 
