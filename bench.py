@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", choices=["fsbm", "acbm"], default=None,
                     help="time only one of the two searches (profiling runs)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB, so that "
+                         "hardware byte counters can be scaled against a known transfer")
     return ap.parse_args()
 
 
@@ -72,8 +75,8 @@ def cpu_baseline(wl, prm_oracle):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -90,6 +93,13 @@ def main():
     prm = acbm.default_params(16, 16, 8)
     npairs = len(frames) - 1
     stream = torch.cuda.Stream(device=dev)
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     fs = acbm.Batch(dev)
     fs_out = fs.add(frames, 16, 16, 32, prm, acbm.ALGO_FSBM)

@@ -157,8 +157,9 @@ SearchPlan plan_search(int N, int M, int p, int max_threads) {
     const double ldsc = (double)(R + M - 1) * N;
     // kWaveFixed: per-wave cost of the window load, the scalar load of the
     // current block and the epilogue reductions, fitted to an R sweep of the
-    // 1920x1088 p = 32 search on MI355X (R = 5, 6 fastest; 2, 3 slowest).
-    constexpr double kWaveFixed = 2000.0;
+    // 1920x1088 p = 32 search on MI355X (R = 6 on 192 threads fastest at
+    // 5.05 ms, then R = 5 and R = 11; R = 3, 4 and 16 slowest).
+    constexpr double kWaveFixed = 400.0;
     const double cost = (double)(threads / 64) * rounds * (std::max(valu, ldsc) + kWaveFixed);
     if (cost < best_cost) {
       best_cost = cost;

@@ -149,21 +149,46 @@ __host__ __device__ inline WindowShape window_shape(int p, int R) {
   return s;
 }
 
-// Cooperative load of the window into LDS (all threads of the group).
+// Cooperative load of the window into LDS (all threads of the group).  Each
+// thread walks (row, dword) positions blockDim.x apart with a carry instead
+// of dividing per element; a window that lies inside the frame (the common
+// case, decided once per block) skips the per-dword bounds test.
 template <int N, int M>
 __device__ inline void load_window(uint32_t* __restrict__ win, const WindowShape& s,
                                    const uint8_t* __restrict__ ref, int pitch, int width,
                                    int height, int x0, int y0) {
   const int xs = x0 + s.u_lo;  // multiple of 4
-  const int total = s.rows * s.dws;
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    const int row = idx / s.dws, dw = idx - row * s.dws;
-    const int y = y0 - s.p + row;
-    const int x = xs + 4 * dw;
-    uint32_t val = 0;
-    if (y >= 0 && y < height && x >= 0 && x + 3 < width)
-      val = *reinterpret_cast<const uint32_t*>(ref + (size_t)y * pitch + x);
-    win[row * s.stride + dw] = val;
+  const int ys = y0 - s.p;
+  const int nt = (int)blockDim.x;
+  const int drow = nt / s.dws, ddw = nt - drow * s.dws;
+  int row = (int)threadIdx.x / s.dws;
+  int dw = (int)threadIdx.x - row * s.dws;
+  const bool inside = xs >= 0 && xs + 4 * s.dws <= width && ys >= 0 && ys + s.rows <= height;
+  if (inside) {
+    const uint8_t* base = ref + (size_t)ys * pitch + xs;
+    while (row < s.rows) {
+      win[row * s.stride + dw] = *reinterpret_cast<const uint32_t*>(base + (size_t)row * pitch + 4 * dw);
+      row += drow;
+      dw += ddw;
+      if (dw >= s.dws) {
+        dw -= s.dws;
+        ++row;
+      }
+    }
+  } else {
+    while (row < s.rows) {
+      const int y = ys + row, x = xs + 4 * dw;
+      uint32_t val = 0;
+      if (y >= 0 && y < height && x >= 0 && x + 3 < width)
+        val = *reinterpret_cast<const uint32_t*>(ref + (size_t)y * pitch + x);
+      win[row * s.stride + dw] = val;
+      row += drow;
+      dw += ddw;
+      if (dw >= s.dws) {
+        dw -= s.dws;
+        ++row;
+      }
+    }
   }
 }
 
