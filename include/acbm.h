@@ -173,8 +173,47 @@ typedef struct acbm_job {
 int acbm_batch_workspace_size(const acbm_job* jobs, size_t njobs, size_t* bytes);
 /* Runs every job; all work is enqueued on `stream` and the call returns
  * without waiting.  Results are identical to running each pair through the
- * *_frame calls in order. */
+ * *_frame calls in order.  FSBM jobs (Section 2.3) are grouped by block size
+ * and window-search plan; each group is one persistent full-search launch
+ * over all (job, pair, block) items of its jobs plus one resolve launch
+ * with a workgroup per pair, reading job tables that small kernels write
+ * into `ws` first.  PBM/ACBM jobs each get their row-pipelined launch.
+ * ws must hold acbm_batch_workspace_size bytes (per-job scratch plus the
+ * tables) and must not be shared by overlapping calls. */
 int acbm_batch(const acbm_job* jobs, size_t njobs, void* ws, size_t ws_bytes, void* stream);
+
+/* A batch recorded once as a HIP graph and replayed with one launch.
+ * create: validates like acbm_batch, then records exactly the sequence
+ *   acbm_batch enqueues (job-table writes, the persistent FSBM groups, the
+ *   PBM/ACBM launches) on a private stream and instantiates it.  Frame
+ *   pointers, `out` arrays, parameters and `ws` are baked in: they must stay
+ *   allocated at the same addresses for the graph's lifetime (their contents
+ *   may change between launches).  The graph holds only kernel nodes (no
+ *   memset or copy nodes).  create synchronises nothing but is not meant for
+ *   a hot loop or for use while the calling thread captures another stream.
+ *   Errors: as acbm_batch, ACBM_E_DEVICE if recording fails.
+ * launch: enqueues the whole batch on `stream` (one hipGraphLaunch) and
+ *   returns without waiting; results are identical to acbm_batch.  Launches
+ *   of one graph must not overlap (they share `ws`).
+ * destroy: call after the last launch has completed. */
+typedef struct acbm_batch_graph acbm_batch_graph;
+int acbm_batch_graph_create(const acbm_job* jobs, size_t njobs, void* ws, size_t ws_bytes,
+                            acbm_batch_graph** out);
+int acbm_batch_graph_launch(acbm_batch_graph* gr, void* stream);
+int acbm_batch_graph_destroy(acbm_batch_graph* gr);
+
+/* ---- autotuning --------------------------------------------------------- */
+/* Times the full-search plans of one (block_w, block_h, p) on this device
+ * (every candidate row blocking R that fits, on a synthetic frame pair of
+ * g's size, after one warm-up) and makes the fastest the plan every later
+ * search of that shape uses (process-wide; acbm_sad_table, acbm_fsbm_frame,
+ * acbm_batch and graphs created afterwards).  The environment variable
+ * ACBM_R still overrides.  Results never depend on the plan, only time does.
+ * best_rows and best_ms (may be NULL) receive the chosen R and its time per
+ * pair in milliseconds.  Allocates and frees scratch device memory and
+ * synchronises `stream`.  Errors: as acbm_fsbm_frame's geometry checks,
+ * ACBM_E_DEVICE. */
+int acbm_autotune(const acbm_geom* g, uint32_t* best_rows, float* best_ms, void* stream);
 
 /* ---- kernel timing ------------------------------------------------------ */
 /* When enabled, every kernel the library launches is bracketed by HIP events

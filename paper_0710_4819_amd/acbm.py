@@ -117,6 +117,10 @@ def lib():
         L.acbm_acbm_frame.argtypes = [P(Geom), P(CParams), vp, vp, vp, vp, vp, sz, vp]
         L.acbm_batch_workspace_size.argtypes = [P(Job), sz, P(sz)]
         L.acbm_batch.argtypes = [P(Job), sz, vp, sz, vp]
+        L.acbm_batch_graph_create.argtypes = [P(Job), sz, vp, sz, P(vp)]
+        L.acbm_batch_graph_launch.argtypes = [vp, vp]
+        L.acbm_batch_graph_destroy.argtypes = [vp]
+        L.acbm_autotune.argtypes = [P(Geom), P(C.c_uint32), P(C.c_float), vp]
         L.acbm_serve.argtypes = [P(ServeCfg), P(vp)]
         L.acbm_serve_submit.argtypes = [vp, C.c_uint32, vp, P(Geom), P(CParams), C.c_uint32,
                                         P(C.c_uint64)]
@@ -268,6 +272,48 @@ class Batch:
         _check(lib().acbm_batch(self.table(), len(self.jobs), ws.data_ptr(), ws.numel(),
                                 _stream(stream)))
         return self.outs
+
+
+class BatchGraph:
+    """A Batch recorded once as a HIP graph (acbm_batch_graph_create); each
+    launch() replays the whole batch with one graph launch.  Keeps the batch
+    (frames, outputs, job table) and the workspace alive."""
+
+    def __init__(self, batch: "Batch", ws: torch.Tensor | None = None):
+        self.batch = batch
+        self.ws = ws if ws is not None else torch.empty(max(256, batch.workspace_size()),
+                                                        dtype=torch.uint8, device=batch.device)
+        self.table = batch.table()
+        self.h = C.c_void_p()
+        _check(lib().acbm_batch_graph_create(self.table, len(batch.jobs), self.ws.data_ptr(),
+                                             self.ws.numel(), C.byref(self.h)))
+
+    def launch(self, stream=None) -> list:
+        _check(lib().acbm_batch_graph_launch(self.h, _stream(stream)))
+        return self.batch.outs
+
+    def close(self):
+        if self.h:
+            _check(lib().acbm_batch_graph_destroy(self.h))
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(block_w: int, block_h: int, p: int, width: int, height: int, pitch: int | None = None,
+             stream=None) -> tuple[int, float]:
+    """Times the window-search plans of (block_w, block_h, p) on a synthetic
+    frame pair of this size and makes the fastest the process-wide plan.
+    Returns (rows per lane R, ms per pair)."""
+    g = Geom(width, height, width if pitch is None else pitch, block_w, block_h, p)
+    r = C.c_uint32()
+    ms = C.c_float()
+    _check(lib().acbm_autotune(C.byref(g), C.byref(r), C.byref(ms), _stream(stream)))
+    return r.value, ms.value
 
 
 class Server:

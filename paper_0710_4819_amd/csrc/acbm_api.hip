@@ -5,8 +5,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 
 #include "acbm_device.h"
 #include "acbm_internal.h"
@@ -129,41 +131,73 @@ int lds_limit() {
 // max_threads = 1024 every task gets its own thread (the full-search kernel
 // keeps all SADs of a block in registers); otherwise tasks loop over a fixed
 // group of max_threads.  R = 0 means no plan fits (window too large for LDS).
+WindowShape window_shape_host(int N, int M, int p, int R) {
+  if (N == 16 && M == 16) return window_shape<16, 16>(p, R);
+  if (N == 16 && M == 8) return window_shape<16, 8>(p, R);
+  if (N == 8 && M == 16) return window_shape<8, 16>(p, R);
+  return window_shape<8, 8>(p, R);
+}
+
+static const int kPlanRs[] = {1, 2, 3, 4, 5, 6, 8, 11, 16};
+
+// One workgroup of ceil(tasks/64) waves per block (or max_threads lanes in
+// rounds); R = 0 when the window does not fit.
+static SearchPlan plan_for(int N, int M, int p, int R, int max_threads, double* cost) {
+  const WindowShape s = window_shape_host(N, M, p, R);
+  const int tasks = s.quads * s.groups;
+  const int lds = s.rows * s.stride * 4;
+  int threads, rounds;
+  if (max_threads >= 1024) {
+    if (tasks > 1024) return SearchPlan{0, 0, 0};
+    threads = (tasks + 63) / 64 * 64;
+    rounds = 1;
+  } else {
+    threads = max_threads;
+    rounds = (tasks + threads - 1) / threads;
+  }
+  if (lds > lds_limit()) return SearchPlan{0, 0, 0};
+  const double valu = (double)R * M * (N / 4) * qsad_cost();
+  const double ldsc = (double)(R + M - 1) * N;
+  // kWaveFixed: per-wave cost of the window load, the scalar load of the
+  // current block and the epilogue reductions, fitted to an R sweep of the
+  // 1920x1088 p = 32 search on MI355X (R = 6 on 192 threads fastest at
+  // 5.05 ms, then R = 5 and R = 11; R = 3, 4 and 16 slowest).
+  constexpr double kWaveFixed = 400.0;
+  *cost = (double)(threads / 64) * rounds * (std::max(valu, ldsc) + kWaveFixed);
+  return SearchPlan{R, threads, lds};
+}
+
+SearchPlan plan_search_model(int N, int M, int p, int R) {
+  double cost = 0;
+  return plan_for(N, M, p, R, 1024, &cost);
+}
+
+namespace {
+std::mutex g_tuned_mu;
+std::map<std::tuple<int, int, int>, SearchPlan> g_tuned;
+}  // namespace
+
+void set_tuned_plan(int N, int M, int p, const SearchPlan& pl) {
+  std::lock_guard<std::mutex> lk(g_tuned_mu);
+  g_tuned[std::make_tuple(N, M, p)] = pl;
+}
+
 SearchPlan plan_search(int N, int M, int p, int max_threads) {
-  static const int Rs[] = {1, 2, 3, 4, 5, 6, 8, 11, 16};
   const char* force = std::getenv("ACBM_R");
+  if (!force && max_threads >= 1024) {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    auto it = g_tuned.find(std::make_tuple(N, M, p));
+    if (it != g_tuned.end()) return it->second;
+  }
   SearchPlan best{0, 0, 0};
   double best_cost = 1e300;
-  for (int R : Rs) {
+  for (int R : kPlanRs) {
     if (force && std::atoi(force) != R) continue;
-    WindowShape s;
-    if (N == 16 && M == 16) s = window_shape<16, 16>(p, R);
-    else if (N == 16 && M == 8) s = window_shape<16, 8>(p, R);
-    else if (N == 8 && M == 16) s = window_shape<8, 16>(p, R);
-    else s = window_shape<8, 8>(p, R);
-    const int tasks = s.quads * s.groups;
-    const int lds = s.rows * s.stride * 4;
-    int threads, rounds;
-    if (max_threads >= 1024) {
-      if (tasks > 1024) continue;
-      threads = (tasks + 63) / 64 * 64;
-      rounds = 1;
-    } else {
-      threads = max_threads;
-      rounds = (tasks + threads - 1) / threads;
-    }
-    if (lds > lds_limit()) continue;
-    const double valu = (double)R * M * (N / 4) * qsad_cost();
-    const double ldsc = (double)(R + M - 1) * N;
-    // kWaveFixed: per-wave cost of the window load, the scalar load of the
-    // current block and the epilogue reductions, fitted to an R sweep of the
-    // 1920x1088 p = 32 search on MI355X (R = 6 on 192 threads fastest at
-    // 5.05 ms, then R = 5 and R = 11; R = 3, 4 and 16 slowest).
-    constexpr double kWaveFixed = 400.0;
-    const double cost = (double)(threads / 64) * rounds * (std::max(valu, ldsc) + kWaveFixed);
-    if (cost < best_cost) {
+    double cost = 0;
+    const SearchPlan pl = plan_for(N, M, p, R, max_threads, &cost);
+    if (pl.R && cost < best_cost) {
       best_cost = cost;
-      best = SearchPlan{R, threads, lds};
+      best = pl;
     }
   }
   return best;

@@ -1,9 +1,24 @@
 // acbm_batch.hip -- many sequences of uneven geometry in one call.
+//
+// FSBM jobs (Section 2.3) are grouped by block size and window-search plan;
+// each group runs as one persistent full-search launch whose workgroups take
+// (job, pair, block) items from a counter, then one resolve launch with a
+// workgroup per pair of every job in the group.  The job tables those
+// launches read are written into the caller's workspace by small kernels
+// whose arguments carry the bytes, so the whole call is stream-ordered and
+// needs no host staging memory.  PBM/ACBM jobs (Sections 2.2, 3.2) keep
+// their own row-pipelined launch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "acbm_internal.h"
+
+#include <cstring>
+#include <memory>
 
 using namespace acbm;
 
@@ -23,24 +38,136 @@ int job_ws(const acbm_job& j, size_t* bytes) {
   }
 }
 
-}  // namespace
+// Everything one acbm_batch call enqueues, planned on the host.
+struct Class {
+  int N = 0, M = 0;
+  SearchPlan pl{};
+  std::vector<BatchJob> jobs;
+  std::vector<size_t> job_index;  // into the caller's job array
+  uint32_t items = 0, pairs = 0;
+  size_t lds_search = 0, lds_resolve = 0;
+};
 
-extern "C" {
+struct Plan {
+  std::vector<size_t> slice;      // workspace offset of each job
+  std::vector<Class> classes;
+  std::vector<size_t> predictive; // PBM/ACBM jobs
+  size_t jobs_bytes = 0;          // job slices
+  size_t table_off = 0, table_bytes = 0;
+  size_t off_jobs = 0, off_ptrs = 0;  // within the table region
+  size_t njob_fsbm = 0, nptr = 0;
+};
 
-int acbm_batch_workspace_size(const acbm_job* jobs, size_t njobs, size_t* bytes) {
-  if (!jobs || !bytes) return fail(ACBM_E_INVAL, "jobs or bytes is NULL");
-  size_t total = 0;
+// Groups the jobs and lays out the workspace: job slices first, then the
+// table region [class counters][BatchJob per FSBM job][frame pointers].
+int make_plan(const acbm_job* jobs, size_t njobs, Plan* pl) {
+  std::map<std::tuple<int, int, int, int>, size_t> cls;
+  size_t off = 0;
+  pl->slice.resize(njobs);
   for (size_t i = 0; i < njobs; ++i) {
+    const acbm_job& j = jobs[i];
     size_t b = 0;
-    int rc = job_ws(jobs[i], &b);
+    int rc = job_ws(j, &b);
     if (rc) return rc;
-    total += b;
+    pl->slice[i] = off;
+    off += b;
+    if (j.algo != ACBM_ALGO_FSBM) {
+      pl->predictive.push_back(i);
+      continue;
+    }
+    KGeom k;
+    check_geom(&j.geom, &k);
+    const SearchPlan sp = plan_search(k.bw, k.bh, k.p);
+    if (!sp.R) return fail(ACBM_E_UNSUPPORTED, "search window does not fit in LDS");
+    const auto key = std::make_tuple(k.bw, k.bh, sp.R, sp.threads);
+    auto it = cls.find(key);
+    if (it == cls.end()) {
+      it = cls.emplace(key, pl->classes.size()).first;
+      pl->classes.emplace_back();
+      pl->classes.back().N = k.bw;
+      pl->classes.back().M = k.bh;
+      pl->classes.back().pl = sp;
+    }
+    Class& c = pl->classes[it->second];
+    const uint32_t npairs = j.nframes - 1;
+    if ((uint64_t)c.items + (uint64_t)npairs * k.nb > 0xFFFFFFFFull)
+      return fail(ACBM_E_RANGE, "too many blocks in one batch group");
+    BatchJob bj{};
+    bj.g = k;
+    bj.s = window_shape_host(k.bw, k.bh, k.p, sp.R);
+    const uint64_t slack64 = (uint64_t)j.params.lambda * (uint64_t)(rate_max(k.p) - 2);
+    bj.slack = slack64 > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)slack64;
+    bj.lam = j.params.lambda;
+    bj.npairs = npairs;
+    bj.item0 = c.items;
+    bj.pair0 = c.pairs;
+    c.items += npairs * (uint32_t)k.nb;
+    c.pairs += npairs;
+    c.lds_search = std::max<size_t>(c.lds_search, (size_t)sp.lds_bytes);
+    if (fsbm_mv_in_lds(k)) c.lds_resolve = std::max<size_t>(c.lds_resolve, (size_t)k.nb * 4);
+    c.jobs.push_back(bj);
+    c.job_index.push_back(i);
+    pl->njob_fsbm += 1;
+    pl->nptr += j.nframes;
   }
-  *bytes = total;
+  pl->jobs_bytes = off;
+  pl->table_off = off;
+  pl->off_jobs = align256(pl->classes.size() * sizeof(uint32_t));
+  pl->off_ptrs = pl->off_jobs + align256(pl->njob_fsbm * sizeof(BatchJob));
+  pl->table_bytes = pl->classes.empty() ? 0 : pl->off_ptrs + align256(pl->nptr * sizeof(void*));
   return ACBM_OK;
 }
 
-int acbm_batch(const acbm_job* jobs, size_t njobs, void* ws, size_t ws_bytes, void* stream) {
+// Up to 448 eight-byte words per launch travel as kernel arguments (under
+// the 4 KiB argument limit) and are stored by one thread each.
+constexpr int kTableWords = 448;
+struct TableChunk {
+  uint64_t w[kTableWords];
+};
+__global__ void k_put_table(uint64_t* __restrict__ dst, const TableChunk c, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = c.w[i];
+}
+
+// Fills the device pointers of the plan and enqueues the table writes.
+int write_tables(const acbm_job* jobs, Plan* pl, char* ws, hipStream_t st) {
+  if (!pl->table_bytes) return ACBM_OK;
+  char* table = ws + pl->table_off;
+  std::vector<uint64_t> host(pl->table_bytes / 8, 0);  // counters start at zero
+  char* hb = reinterpret_cast<char*>(host.data());
+  size_t jo = 0, po = 0;
+  for (Class& c : pl->classes) {
+    for (size_t n = 0; n < c.jobs.size(); ++n) {
+      const acbm_job& j = jobs[c.job_index[n]];
+      BatchJob& bj = c.jobs[n];
+      char* sl = ws + pl->slice[c.job_index[n]];
+      bj.recs = reinterpret_cast<BlockRec*>(sl + fsbm_recs_offset());
+      bj.ovf = reinterpret_cast<uint16_t*>(sl + fsbm_ovf_offset(bj.g, bj.npairs));
+      bj.mv_ws = fsbm_mv_in_lds(bj.g) ? nullptr
+                                      : reinterpret_cast<uint32_t*>(sl + fsbm_mv_offset(bj.g, bj.npairs));
+      bj.out = j.out;
+      bj.frames = reinterpret_cast<const uint8_t* const*>(table + pl->off_ptrs + po * sizeof(void*));
+      std::memcpy(hb + pl->off_ptrs + po * sizeof(void*), j.frames, j.nframes * sizeof(void*));
+      po += j.nframes;
+    }
+    std::memcpy(hb + pl->off_jobs + jo * sizeof(BatchJob), c.jobs.data(),
+                c.jobs.size() * sizeof(BatchJob));
+    jo += c.jobs.size();
+  }
+  uint64_t* dst = reinterpret_cast<uint64_t*>(table);
+  const size_t nw = host.size();
+  for (size_t k = 0; k < nw; k += kTableWords) {
+    const int n = (int)std::min<size_t>(kTableWords, nw - k);
+    TableChunk chunk;
+    std::memcpy(chunk.w, host.data() + k, (size_t)n * 8);
+    hipLaunchKernelGGL(k_put_table, dim3((n + 63) / 64), dim3(64), 0, st, dst + k, chunk, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "writing the batch job table");
+  }
+  return ACBM_OK;
+}
+
+int validate_jobs(const acbm_job* jobs, size_t njobs, void* ws, size_t ws_bytes) {
   if (!jobs && njobs) return fail(ACBM_E_INVAL, "jobs is NULL");
   size_t need = 0;
   int rc = acbm_batch_workspace_size(jobs, njobs, &need);
@@ -54,23 +181,120 @@ int acbm_batch(const acbm_job* jobs, size_t njobs, void* ws, size_t ws_bytes, vo
     for (uint32_t f = 0; f < j.nframes; ++f)
       if ((rc = check_frame_ptr(j.frames[f], "frame"))) return rc;
   }
-  if ((rc = check_device())) return rc;
+  return check_device();
+}
+
+}  // namespace
+
+extern "C" {
+
+int acbm_batch_workspace_size(const acbm_job* jobs, size_t njobs, size_t* bytes) {
+  if (!jobs || !bytes) return fail(ACBM_E_INVAL, "jobs or bytes is NULL");
+  Plan pl;
+  int rc = make_plan(jobs, njobs, &pl);
+  if (rc) return rc;
+  *bytes = pl.jobs_bytes + pl.table_bytes;
+  return ACBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Enqueues every job of a validated batch on `st`: the job tables first,
+// then one persistent search and one resolve launch per FSBM group, then the
+// row-pipelined PBM/ACBM jobs.  Kernels only, so the sequence can be
+// recorded into a graph as it is.
+int enqueue_batch(const acbm_job* jobs, size_t njobs, void* ws, hipStream_t st) {
+  Plan pl;
+  int rc = make_plan(jobs, njobs, &pl);
+  if (rc) return rc;
   char* base = static_cast<char*>(ws);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  for (size_t i = 0; i < njobs; ++i) {
+  if ((rc = write_tables(jobs, &pl, base, st))) return rc;
+  size_t jo = 0;
+  for (size_t ci = 0; ci < pl.classes.size(); ++ci) {
+    const Class& c = pl.classes[ci];
+    const BatchJob* dj =
+        reinterpret_cast<const BatchJob*>(base + pl.table_off + pl.off_jobs + jo * sizeof(BatchJob));
+    uint32_t* counter = reinterpret_cast<uint32_t*>(base + pl.table_off) + ci;
+    rc = launch_search_batch(c.N, c.M, c.pl, c.lds_search, dj, (int)c.jobs.size(), c.items,
+                             counter, st);
+    if (!rc) rc = launch_resolve_batch(dj, (int)c.jobs.size(), c.pairs, c.lds_resolve, st);
+    if (rc) return rc;
+    jo += c.jobs.size();
+  }
+  for (size_t i : pl.predictive) {
     const acbm_job& j = jobs[i];
     KGeom k;
     check_geom(&j.geom, &k);
     size_t b = 0;
     job_ws(j, &b);
-    const uint32_t npairs = j.nframes - 1;
-    if (j.algo == ACBM_ALGO_FSBM)
-      rc = launch_fsbm(k, j.params, j.frames, npairs, base, b, j.out, st);
-    else
-      rc = launch_predictive(k, j.params, (int)j.algo, j.frames, npairs, nullptr, base, b, j.out, st);
+    rc = launch_predictive(k, j.params, (int)j.algo, j.frames, j.nframes - 1, nullptr,
+                           base + pl.slice[i], b, j.out, st);
     if (rc) return rc;
-    base += b;
   }
+  return ACBM_OK;
+}
+
+}  // namespace
+
+struct acbm_batch_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~acbm_batch_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+extern "C" {
+
+int acbm_batch(const acbm_job* jobs, size_t njobs, void* ws, size_t ws_bytes, void* stream) {
+  int rc = validate_jobs(jobs, njobs, ws, ws_bytes);
+  if (rc) return rc;
+  return enqueue_batch(jobs, njobs, ws, static_cast<hipStream_t>(stream));
+}
+
+int acbm_batch_graph_create(const acbm_job* jobs, size_t njobs, void* ws, size_t ws_bytes,
+                            acbm_batch_graph** out) {
+  if (!out) return fail(ACBM_E_INVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate_jobs(jobs, njobs, ws, ws_bytes);
+  if (rc) return rc;
+  hipStream_t st = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "creating the capture stream");
+  e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(st);
+    return hip_fail(e, "beginning the batch capture");
+  }
+  rc = enqueue_batch(jobs, njobs, ws, st);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(st, &graph);
+  (void)hipStreamDestroy(st);
+  if (!rc && e != hipSuccess) rc = hip_fail(e, "ending the batch capture");
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  auto gr = std::make_unique<acbm_batch_graph>();
+  gr->graph = graph;
+  e = hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return hip_fail(e, "instantiating the batch graph");
+  *out = gr.release();
+  return ACBM_OK;
+}
+
+int acbm_batch_graph_launch(acbm_batch_graph* gr, void* stream) {
+  if (!gr || !gr->exec) return fail(ACBM_E_INVAL, "graph is NULL");
+  hipError_t e = hipGraphLaunch(gr->exec, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? ACBM_OK : hip_fail(e, "launching the batch graph");
+}
+
+int acbm_batch_graph_destroy(acbm_batch_graph* gr) {
+  if (!gr) return fail(ACBM_E_INVAL, "graph is NULL");
+  delete gr;
   return ACBM_OK;
 }
 

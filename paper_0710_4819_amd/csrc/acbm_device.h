@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "acbm_internal.h"
+
 namespace acbm {
 
 // ---------------------------------------------------------------------------
@@ -127,15 +129,6 @@ __device__ __forceinline__ uint64_t group_min_u64(uint64_t x, uint64_t* scratch)
 // v = -p + R*g ... -p + R*g + R - 1.  Bytes outside the frame read as 0; the
 // candidates that touch them are invalid and masked afterwards.
 // ---------------------------------------------------------------------------
-struct WindowShape {
-  int p, u_lo;
-  int quads;   // QX: quads per window row of candidates
-  int groups;  // row groups of R candidate rows
-  int rows;    // LDS rows (>= groups*R + M - 1)
-  int dws;     // dwords per LDS row (>= quads + N/4)
-  int stride;  // LDS row stride in dwords
-};
-
 template <int N, int M>
 __host__ __device__ inline WindowShape window_shape(int p, int R) {
   WindowShape s;

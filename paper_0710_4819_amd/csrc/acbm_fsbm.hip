@@ -59,21 +59,18 @@ __device__ __forceinline__ uint32_t wave_intra_x(const uint8_t* __restrict__ cur
 }
 
 // ---------------------------------------------------------------------------
-// Window search.  kTable: write the u32 table; else: write BlockRec + overflow.
+// Window search of one block (all threads of the group).  kTable: write the
+// block's u32 table `tab`; else write its BlockRec `rec` and, when more than
+// kShort candidates can win, its overflow row `row`.  `win` is the window
+// in LDS, `red` one slot per wave, `n_keep` a shared counter.
 // ---------------------------------------------------------------------------
 template <int N, int M, int R, bool kTable>
-__global__ void __launch_bounds__(1024)
-k_search(const KGeom g, const WindowShape s, const FramePtrs fr, uint32_t* __restrict__ table,
-         BlockRec* __restrict__ recs, uint16_t* __restrict__ ovf, uint32_t slack) {
-  extern __shared__ uint32_t win[];
-  __shared__ uint64_t red[16];
-  __shared__ uint32_t n_keep;
-
-  const int b = xcd_band(blockIdx.x, g.nb);
-  if (b >= g.nb) return;
-  const int pair = blockIdx.y;
-  const uint8_t* __restrict__ ref = fr.f[pair];
-  const uint8_t* __restrict__ cur = fr.f[pair + 1];
+__device__ __forceinline__ void search_block(const KGeom& g, const WindowShape& s,
+                                             const uint8_t* __restrict__ ref,
+                                             const uint8_t* __restrict__ cur, int b,
+                                             uint32_t* __restrict__ tab, BlockRec* __restrict__ rec,
+                                             uint16_t* __restrict__ row, uint32_t slack,
+                                             uint32_t* win, uint64_t* red, uint32_t* n_keep) {
   const int r = b / g.bx, c = b - r * g.bx;
   const int x0 = c * N, y0 = r * M;
   const int p = s.p, W = 2 * p + 1;
@@ -83,7 +80,7 @@ k_search(const KGeom g, const WindowShape s, const FramePtrs fr, uint32_t* __res
   load_cur_uniform<N, M>(cb, cur, g.pitch, x0, y0);
   uint32_t intra = 0;
   if (!kTable && threadIdx.x < 64) intra = wave_intra_x<N, M>(cur, g.pitch, x0, y0);
-  if (threadIdx.x == 0) n_keep = 0;
+  if (threadIdx.x == 0) *n_keep = 0;
   __syncthreads();
 
   const int tasks = s.quads * s.groups;
@@ -102,7 +99,6 @@ k_search(const KGeom g, const WindowShape s, const FramePtrs fr, uint32_t* __res
 
   if (kTable) {
     if (!active) return;
-    uint32_t* out = table + (size_t)b * W * W;
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
       const int v = v0 + rr;
@@ -112,7 +108,7 @@ k_search(const KGeom g, const WindowShape s, const FramePtrs fr, uint32_t* __res
         const int u = u0 + i;
         if (u < -p || u > p) continue;
         const uint32_t sad = (uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu;
-        out[(v + p) * W + (u + p)] = sad == 0xFFFFu ? 0xFFFFFFFFu : sad;
+        tab[(v + p) * W + (u + p)] = sad == 0xFFFFu ? 0xFFFFFFFFu : sad;
       }
     }
     return;
@@ -123,14 +119,13 @@ k_search(const KGeom g, const WindowShape s, const FramePtrs fr, uint32_t* __res
   const uint32_t smin = (uint32_t)group_min_u64(lmin, red);
   const uint32_t thr = (uint32_t)min<uint64_t>((uint64_t)smin + slack, 0xFFFEu);
 
-  BlockRec* rec = recs + ((size_t)pair * g.nb + b);
   if (active && lmin <= thr) {  // rare: this lane holds a possible winner
     uint32_t mine = 0;
 #pragma unroll
     for (int rr = 0; rr < R; ++rr)
 #pragma unroll
       for (int i = 0; i < 4; ++i) mine += ((uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu) <= thr;
-    uint32_t slot = atomicAdd(&n_keep, mine);
+    uint32_t slot = atomicAdd(n_keep, mine);
 #pragma unroll
     for (int rr = 0; rr < R; ++rr)
 #pragma unroll
@@ -144,9 +139,8 @@ k_search(const KGeom g, const WindowShape s, const FramePtrs fr, uint32_t* __res
       }
   }
   __syncthreads();
-  const uint32_t total = n_keep;
+  const uint32_t total = *n_keep;
   if (total > (uint32_t)kShort && active) {
-    uint16_t* row = ovf + ((size_t)pair * g.nb + b) * (size_t)(W * W);
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
       const int v = v0 + rr;
@@ -164,6 +158,68 @@ k_search(const KGeom g, const WindowShape s, const FramePtrs fr, uint32_t* __res
     rec->count = total;
     rec->intra_x = intra;
   }
+}
+
+// One workgroup per (block, pair).
+template <int N, int M, int R, bool kTable>
+__global__ void __launch_bounds__(1024)
+k_search(const KGeom g, const WindowShape s, const FramePtrs fr, uint32_t* __restrict__ table,
+         BlockRec* __restrict__ recs, uint16_t* __restrict__ ovf, uint32_t slack) {
+  extern __shared__ uint32_t win[];
+  __shared__ uint64_t red[16];
+  __shared__ uint32_t n_keep;
+  const int b = xcd_band(blockIdx.x, g.nb);
+  if (b >= g.nb) return;
+  const int pair = blockIdx.y;
+  const size_t WW = (size_t)(2 * s.p + 1) * (2 * s.p + 1);
+  const size_t at = (size_t)pair * g.nb + b;
+  search_block<N, M, R, kTable>(g, s, fr.f[pair], fr.f[pair + 1], b,
+                                kTable ? table + (size_t)b * WW : nullptr,
+                                kTable ? nullptr : recs + at, kTable ? nullptr : ovf + at * WW,
+                                slack, win, red, &n_keep);
+}
+
+// Persistent full search over the jobs of one batch class: workgroups take
+// (job, pair, block) items from one counter until none are left.
+template <int N, int M, int R>
+__global__ void __launch_bounds__(1024)
+k_search_batch(const BatchJob* __restrict__ jobs, int njobs, uint32_t items,
+               uint32_t* __restrict__ counter) {
+  extern __shared__ uint32_t win[];
+  __shared__ uint64_t red[16];
+  __shared__ uint32_t n_keep, sh_item;
+  // Item fetch: thread 0 takes the next item, a barrier publishes it, and
+  // readfirstlane makes it wave-uniform for the compiler.  Every iteration
+  // ends with a barrier before the next fetch, so no thread-0-only region
+  // spans the loop's back edge: otherwise the control-flow structurizer may
+  // turn the loop (which contains barriers) into a nest in which the lanes
+  // other than thread 0 re-run the same item and never exit.
+  if (threadIdx.x == 0) sh_item = atomicAdd(counter, 1u);
+  __syncthreads();
+  uint32_t it = __builtin_amdgcn_readfirstlane(sh_item);
+  while (it < items) {
+    int j = 0;
+    while (j + 1 < njobs && jobs[j + 1].item0 <= it) ++j;
+    j = __builtin_amdgcn_readfirstlane(j);
+    const BatchJob& J = jobs[j];
+    const KGeom g = J.g;
+    const uint32_t local = it - J.item0;
+    const int pair = (int)(local / (uint32_t)g.nb), b = (int)(local % (uint32_t)g.nb);
+    const size_t WW = (size_t)(2 * g.p + 1) * (2 * g.p + 1);
+    const size_t at = (size_t)pair * g.nb + b;
+    search_block<N, M, R, false>(g, J.s, J.frames[pair], J.frames[pair + 1], b, nullptr,
+                                 J.recs + at, J.ovf + at * WW, J.slack, win, red, &n_keep);
+    __syncthreads();
+    if (threadIdx.x == 0) sh_item = atomicAdd(counter, 1u);
+    __syncthreads();
+    it = __builtin_amdgcn_readfirstlane(sh_item);
+  }
+}
+
+// Sets n counters to zero (a kernel, so that it can sit in a graph).
+__global__ void k_zero_u32(uint32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -235,21 +291,15 @@ __device__ __forceinline__ uint64_t wave_block_argmin(const BlockRec* __restrict
   return wave_min_u64(best);
 }
 
-// One workgroup per frame pair.  The state lives in LDS when it fits
-// (st_global == nullptr), else in a workspace array; either way only this
-// workgroup touches it.
-__global__ void __launch_bounds__(1024)
-k_resolve(const KGeom g, const BlockRec* __restrict__ recs, const uint16_t* __restrict__ ovf,
-          acbm_block_result* __restrict__ out, uint32_t lam, uint32_t* st_global) {
-  extern __shared__ uint32_t st_lds[];
-  __shared__ int pending;
-  const int pair = blockIdx.x;
+// FSBM resolve of one frame pair by the whole group.  `st` is the pair's
+// decision state (LDS or workspace); `pending` a shared flag.
+__device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __restrict__ recs,
+                                             const uint16_t* __restrict__ ovf,
+                                             acbm_block_result* __restrict__ out, uint32_t lam,
+                                             uint32_t* st, int* pending_flag) {
+  int& pending = *pending_flag;
   const int p = g.p, W = 2 * p + 1, nb = g.nb, bx = g.bx;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  uint32_t* st = st_global ? st_global + (size_t)pair * nb : st_lds;
-  recs += (size_t)pair * nb;
-  ovf += (size_t)pair * nb * (size_t)(W * W);
-  out += (size_t)pair * nb;
 
   // blocks with a single possible winner are decided without a predictor
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
@@ -298,7 +348,9 @@ k_resolve(const KGeom g, const BlockRec* __restrict__ recs, const uint16_t* __re
       }
     }
     __syncthreads();
-    const int again = pending;
+    // one LDS word, uniform; readfirstlane keeps the break (the loop contains
+    // barriers) a uniform branch for the compiler
+    const int again = __builtin_amdgcn_readfirstlane(pending);
     __syncthreads();
     if (!again) break;
   }
@@ -322,6 +374,39 @@ k_resolve(const KGeom g, const BlockRec* __restrict__ recs, const uint16_t* __re
     res.intra_x = recs[b].intra_x;
     out[b] = res;
   }
+}
+
+// One workgroup per frame pair.  The state lives in LDS when it fits
+// (st_global == nullptr), else in a workspace array; either way only this
+// workgroup touches it.
+__global__ void __launch_bounds__(1024)
+k_resolve(const KGeom g, const BlockRec* __restrict__ recs, const uint16_t* __restrict__ ovf,
+          acbm_block_result* __restrict__ out, uint32_t lam, uint32_t* st_global) {
+  extern __shared__ uint32_t st_lds[];
+  __shared__ int pending;
+  const int pair = blockIdx.x;
+  const size_t WW = (size_t)(2 * g.p + 1) * (2 * g.p + 1);
+  resolve_pair(g, recs + (size_t)pair * g.nb, ovf + (size_t)pair * g.nb * WW,
+               out + (size_t)pair * g.nb, lam,
+               st_global ? st_global + (size_t)pair * g.nb : st_lds, &pending);
+}
+
+// The resolves of every pair of one batch class: one workgroup per pair.
+__global__ void __launch_bounds__(1024)
+k_resolve_batch(const BatchJob* __restrict__ jobs, int njobs) {
+  extern __shared__ uint32_t st_lds[];
+  __shared__ int pending;
+  const uint32_t wg = blockIdx.x;
+  int j = 0;
+  while (j + 1 < njobs && jobs[j + 1].pair0 <= wg) ++j;
+  j = __builtin_amdgcn_readfirstlane(j);  // uniform: the resolve loops contain barriers
+  const BatchJob& J = jobs[j];
+  const KGeom g = J.g;
+  const int pair = (int)(wg - J.pair0);
+  const size_t WW = (size_t)(2 * g.p + 1) * (2 * g.p + 1);
+  resolve_pair(g, J.recs + (size_t)pair * g.nb, J.ovf + (size_t)pair * g.nb * WW,
+               J.out + (size_t)pair * g.nb, J.lam,
+               J.mv_ws ? J.mv_ws + (size_t)pair * g.nb : st_lds, &pending);
 }
 
 // ---------------------------------------------------------------------------
@@ -357,9 +442,9 @@ static int launch_search_nm(const KGeom& g, const SearchPlan& pl, const FramePtr
 }
 
 template <bool kTable>
-static int launch_search(const KGeom& g, const FramePtrs& fr, int npairs, uint32_t* table,
-                         BlockRec* recs, uint16_t* ovf, uint32_t slack, hipStream_t st) {
-  const SearchPlan pl = plan_search(g.bw, g.bh, g.p);
+static int launch_search_with(const KGeom& g, const SearchPlan& pl, const FramePtrs& fr,
+                              int npairs, uint32_t* table, BlockRec* recs, uint16_t* ovf,
+                              uint32_t slack, hipStream_t st) {
   if (!pl.R) return fail(ACBM_E_UNSUPPORTED, "search window does not fit in LDS");
   if (g.bw == 16 && g.bh == 16)
     return launch_search_nm<16, 16, kTable>(g, pl, fr, npairs, table, recs, ovf, slack, st);
@@ -370,6 +455,89 @@ static int launch_search(const KGeom& g, const FramePtrs& fr, int npairs, uint32
   if (g.bw == 8 && g.bh == 8)
     return launch_search_nm<8, 8, kTable>(g, pl, fr, npairs, table, recs, ovf, slack, st);
   return fail(ACBM_E_UNSUPPORTED, "block size must be 8 or 16 in each direction");
+}
+
+template <bool kTable>
+static int launch_search(const KGeom& g, const FramePtrs& fr, int npairs, uint32_t* table,
+                         BlockRec* recs, uint16_t* ovf, uint32_t slack, hipStream_t st) {
+  return launch_search_with<kTable>(g, plan_search(g.bw, g.bh, g.p), fr, npairs, table, recs,
+                                    ovf, slack, st);
+}
+
+int launch_search_plan(const KGeom& g, const SearchPlan& pl, const uint8_t* const* frames,
+                       int npairs, BlockRec* recs, uint16_t* ovf, uint32_t slack,
+                       hipStream_t st) {
+  if (npairs > kMaxPairsPerLaunch) return fail(ACBM_E_INVAL, "too many pairs for one search");
+  FramePtrs fr{};
+  for (int k = 0; k <= npairs; ++k) fr.f[k] = frames[k];
+  return launch_search_with<false>(g, pl, fr, npairs, nullptr, recs, ovf, slack, st);
+}
+
+// Persistent batch kernels ---------------------------------------------------
+static int device_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+  }
+  return cus;
+}
+
+template <int N, int M>
+static int launch_search_batch_nm(const SearchPlan& pl, size_t lds, const BatchJob* jobs,
+                                  int njobs, uint32_t items, uint32_t* counter, hipStream_t st) {
+  switch (pl.R) {
+#define ACBM_CASE(RR)                                                                         \
+  case RR: {                                                                                  \
+    const void* fn = (const void*)k_search_batch<N, M, RR>;                                   \
+    if (lds > 64 * 1024)                                                                      \
+      (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);    \
+    int per_cu = 0;                                                                           \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, pl.threads, lds) !=         \
+            hipSuccess ||                                                                     \
+        per_cu < 1)                                                                           \
+      per_cu = 1;                                                                             \
+    const int grid = (int)std::min<uint64_t>((uint64_t)device_cus() * per_cu, items);         \
+    ProfScope ps("search", st);                                                               \
+    hipLaunchKernelGGL((k_search_batch<N, M, RR>), dim3(grid), dim3(pl.threads), lds, st,     \
+                       jobs, njobs, items, counter);                                          \
+    break;                                                                                    \
+  }
+    ACBM_R_LIST(ACBM_CASE)
+#undef ACBM_CASE
+    default:
+      return fail(ACBM_E_UNSUPPORTED, "no search kernel for this row blocking");
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ACBM_OK : hip_fail(e, "launching the batched window search");
+}
+
+int launch_search_batch(int N, int M, const SearchPlan& pl, size_t lds, const BatchJob* jobs,
+                        int njobs, uint32_t items, uint32_t* counter, hipStream_t st) {
+  if (!items) return ACBM_OK;
+  if (N == 16 && M == 16) return launch_search_batch_nm<16, 16>(pl, lds, jobs, njobs, items, counter, st);
+  if (N == 16 && M == 8) return launch_search_batch_nm<16, 8>(pl, lds, jobs, njobs, items, counter, st);
+  if (N == 8 && M == 16) return launch_search_batch_nm<8, 16>(pl, lds, jobs, njobs, items, counter, st);
+  if (N == 8 && M == 8) return launch_search_batch_nm<8, 8>(pl, lds, jobs, njobs, items, counter, st);
+  return fail(ACBM_E_UNSUPPORTED, "block size must be 8 or 16 in each direction");
+}
+
+int launch_resolve_batch(const BatchJob* jobs, int njobs, uint32_t pairs, size_t lds,
+                         hipStream_t st) {
+  if (!pairs) return ACBM_OK;
+  ProfScope ps("resolve", st);
+  hipLaunchKernelGGL(k_resolve_batch, dim3(pairs), dim3(1024), lds, st, jobs, njobs);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ACBM_OK : hip_fail(e, "launching the batched resolve");
+}
+
+int launch_zero_u32(uint32_t* p, int n, hipStream_t st) {
+  if (n <= 0) return ACBM_OK;
+  hipLaunchKernelGGL(k_zero_u32, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ACBM_OK : hip_fail(e, "launching a counter reset");
 }
 
 int launch_sad_table(const KGeom& g, const uint8_t* cur, const uint8_t* ref, uint32_t* table,
@@ -387,6 +555,15 @@ static size_t ovf_row_bytes(const KGeom& g) {
 
 // State of the resolve kernel stays in LDS up to this many bytes.
 constexpr size_t kResolveLdsMax = 48 * 1024;
+
+size_t fsbm_recs_offset() { return align256(sizeof(WsHeader)); }
+size_t fsbm_ovf_offset(const KGeom& g, uint32_t npairs) {
+  return fsbm_recs_offset() + align256((size_t)npairs * g.nb * sizeof(BlockRec));
+}
+size_t fsbm_mv_offset(const KGeom& g, uint32_t npairs) {
+  return fsbm_ovf_offset(g, npairs) + align256((size_t)npairs * g.nb * ovf_row_bytes(g));
+}
+bool fsbm_mv_in_lds(const KGeom& g) { return (size_t)g.nb * sizeof(uint32_t) <= kResolveLdsMax; }
 
 size_t fsbm_ws_bytes(const KGeom& g, uint32_t npairs) {
   const size_t mv_bytes = (size_t)g.nb * sizeof(uint32_t) > kResolveLdsMax

@@ -37,6 +37,33 @@ struct FramePtrs {
   const uint8_t* f[kMaxPairsPerLaunch + 1];
 };
 
+// Shape of a block's search window in LDS (see window_shape in
+// acbm_device.h): rows y0-p .. of dws dwords starting at x0 + u_lo; the lane
+// work unit is one quad of candidates x R candidate rows.
+struct WindowShape {
+  int p, u_lo;
+  int quads;   // QX: quads per window row of candidates
+  int groups;  // row groups of R candidate rows
+  int rows;    // LDS rows (>= groups*R + M - 1)
+  int dws;     // dwords per LDS row (>= quads + N/4)
+  int stride;  // LDS row stride in dwords
+};
+
+// One FSBM job of a batch class as the persistent batch kernels read it
+// (device memory).  Search items are (pair, block) in pair-major order,
+// numbered from item0 within the class; resolve workgroups from pair0.
+struct BatchJob {
+  KGeom g;
+  WindowShape s;
+  const uint8_t* const* frames;  // [npairs + 1] device pointers
+  BlockRec* recs;                // [npairs][nb]
+  uint16_t* ovf;                 // [npairs][nb][(2p+1)^2]
+  acbm_block_result* out;        // [npairs][nb]
+  uint32_t* mv_ws;               // [npairs][nb] resolve state if it does not fit in LDS, else null
+  uint32_t slack, lam, npairs;
+  uint32_t item0, pair0;
+};
+
 // Launch plan of the window search for one (N, M, p).
 struct SearchPlan {
   int R;        // candidate rows per lane
@@ -68,7 +95,13 @@ int check_params(const acbm_params* prm, const KGeom& k);
 int check_frame_ptr(const void* p, const char* what);
 int check_device();
 
+// The window shape the search kernels use for (N, M, p, R).
+WindowShape window_shape_host(int N, int M, int p, int R);
 SearchPlan plan_search(int N, int M, int p, int max_threads = 1024);
+// Plans by the cost model only (the candidates the autotuner times).
+SearchPlan plan_search_model(int N, int M, int p, int R);
+// Records a measured plan for (N, M, p); plan_search returns it from then on.
+void set_tuned_plan(int N, int M, int p, const SearchPlan& pl);
 
 // Brackets one kernel launch with timing events when profiling is on
 // (acbm_profile_enable); a no-op otherwise.
@@ -92,6 +125,21 @@ size_t fsbm_ws_bytes(const KGeom& g, uint32_t npairs);
 int launch_fsbm(const KGeom& g, const acbm_params& prm, const uint8_t* const* frames,
                 uint32_t npairs, void* ws, size_t ws_bytes, acbm_block_result* out,
                 hipStream_t s);
+// Window search with an explicit plan, over `npairs` pairs of one job
+// (kTable = false: BlockRec + overflow rows).
+int launch_search_plan(const KGeom& g, const SearchPlan& pl, const uint8_t* const* frames,
+                       int npairs, BlockRec* recs, uint16_t* ovf, uint32_t slack,
+                       hipStream_t s);
+size_t fsbm_recs_offset();                    // BlockRec array offset in an FSBM workspace
+size_t fsbm_ovf_offset(const KGeom& g, uint32_t npairs);
+size_t fsbm_mv_offset(const KGeom& g, uint32_t npairs);  // resolve state, if used
+bool fsbm_mv_in_lds(const KGeom& g);
+// Persistent kernels of one batch class (jobs with the same N, M and plan).
+int launch_search_batch(int N, int M, const SearchPlan& pl, size_t lds, const BatchJob* jobs,
+                        int njobs, uint32_t items, uint32_t* counter, hipStream_t s);
+int launch_resolve_batch(const BatchJob* jobs, int njobs, uint32_t pairs, size_t lds,
+                         hipStream_t s);
+int launch_zero_u32(uint32_t* p, int n, hipStream_t s);
 size_t predictive_ws_bytes(const KGeom& g, uint32_t npairs);
 int launch_predictive(const KGeom& g, const acbm_params& prm, int algo,
                       const uint8_t* const* frames, uint32_t npairs, const acbm_mv* prev_field,

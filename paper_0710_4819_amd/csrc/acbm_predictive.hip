@@ -449,9 +449,12 @@ k_predictive(const PredArgs a) {
       sh_abort = status_of(a.hdr) != 0;
     }
     __syncthreads();
-    if (sh_row < 0 || sh_abort) return;
-    const int t = __builtin_amdgcn_readfirstlane(sh_row >> 16);
-    const int r = __builtin_amdgcn_readfirstlane(sh_row & 0xFFFF);
+    // LDS words are uniform; readfirstlane lets the compiler see that, so the
+    // exits of this loop (which contains barriers) stay uniform branches
+    const int row_word = __builtin_amdgcn_readfirstlane(sh_row);
+    if (row_word < 0 || __builtin_amdgcn_readfirstlane(sh_abort)) return;
+    const int t = row_word >> 16;
+    const int r = row_word & 0xFFFF;
     const int y0 = r * M;
     const uint8_t* __restrict__ ref = a.frames[t];
     const uint8_t* __restrict__ cur = a.frames[t + 1];
@@ -578,9 +581,10 @@ k_predictive(const PredArgs a) {
         }
       }
       __syncthreads();
-      if (sh_abort) return;
-      const int px = sh_px, py = sh_py;
-      const int np = sh_np;
+      if (__builtin_amdgcn_readfirstlane(sh_abort)) return;
+      const int px = __builtin_amdgcn_readfirstlane(sh_px);
+      const int py = __builtin_amdgcn_readfirstlane(sh_py);
+      const int np = __builtin_amdgcn_readfirstlane(sh_np);
 
       // ---- B: predictor neighbourhoods (all waves).  The predictor state is
       //         copied to registers before the barrier: once past it, wave 0

@@ -62,6 +62,10 @@ int drain(bool wait) {
 ProfScope::ProfScope(const char* name, hipStream_t st) : name_(name), st_(st) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return;
+  // launches recorded into a graph are not timed here (their events would
+  // be graph nodes, not something this process can wait for)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   a_ = take_event();
   if (a_ && hipEventRecord((hipEvent_t)a_, st_) != hipSuccess) a_ = nullptr;
 }
