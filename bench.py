@@ -48,8 +48,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--frames", type=int, default=60)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["fsbm", "acbm"], default=None,
-                    help="time only one of the two searches (profiling runs)")
+    ap.add_argument("--only", choices=["fsbm", "acbm", "batch", "serve"], default=None,
+                    help="run only one leg (profiling runs)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-sequence leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-requests leg")
+    ap.add_argument("--serve-seconds", type=float, default=1.5,
+                    help="duration of each arrival rate of the served leg")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB, so that "
                          "hardware byte counters can be scaled against a known transfer")
@@ -70,6 +74,135 @@ def cpu_baseline(wl, prm_oracle):
             "sample": "FSBM + ACBM of pair 1 of the 1920x1088 p=32 sequence, single thread, "
                       f"{dt:.1f} s, {evals / 1e9:.2f} G evals",
             "seconds": round(dt, 2)}
+
+
+def batched_leg(torch, acbm, synth, dev, reps=5):
+    """64 sequences x 8 frames of mixed resolution, p and block size (FSBM):
+    the graph-recorded batch against the eager batch call and against one
+    acbm_fsbm_frame call per frame pair, all on one stream, inputs resident."""
+    seqs = [synth.batch_sequence(s) for s in range(64)]
+    # tune each (block size, p) on the largest frame that uses it
+    largest = {}
+    for w in seqs:
+        key = (w.block_w, w.block_h, w.p)
+        if key not in largest or w.width * w.height > largest[key][0] * largest[key][1]:
+            largest[key] = (w.width, w.height)
+    tuned = {}
+    for key, (wd, ht) in sorted(largest.items()):
+        R, ms = acbm.autotune(key[0], key[1], key[2], wd, ht)
+        tuned[key] = {"R": R, "ms_per_pair": ms, "tuned_on": f"{wd}x{ht}"}
+    st = torch.cuda.Stream(device=dev)
+    b = acbm.Batch(dev)
+    dframes, prms = [], []
+    for w in seqs:
+        fr = [torch.from_numpy(f).to(dev) for f in w.frames]
+        prm = acbm.default_params(w.block_w, w.block_h, w.lam)
+        b.add(fr, w.block_w, w.block_h, w.p, prm, acbm.ALGO_FSBM)
+        dframes.append(fr)
+        prms.append(prm)
+    ws = torch.empty(max(256, b.workspace_size()), dtype=torch.uint8, device=dev)
+    gr = acbm.BatchGraph(b, ws)
+    # one workspace and result buffer per sequence for the per-frame calls
+    pf_ws = [acbm.workspace(acbm.OP_FSBM, acbm.geom(fr[0], w.block_w, w.block_h, w.p), dev)
+             for w, fr in zip(seqs, dframes)]
+    torch.cuda.synchronize()
+
+    def per_frame():
+        outs = []
+        for w, fr, prm, wsb in zip(seqs, dframes, prms, pf_ws):
+            for t in range(1, len(fr)):
+                outs.append(acbm.fsbm_frame(fr[t], fr[t - 1], w.block_w, w.block_h, w.p, prm,
+                                            ws=wsb, stream=st))
+        return outs
+
+    def timed(fn, n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(st):
+            fn()  # warm-up
+            e0.record(st)
+            t0 = time.perf_counter()
+            for _ in range(n):
+                fn()
+            e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n, (time.perf_counter() - t0) * 1e3 / n
+
+    g_ms, g_wall = timed(lambda: gr.launch(st), reps)
+    res = [acbm.to_numpy(o) for o in b.outs]
+    e_ms, e_wall = timed(lambda: b.run(ws, st), reps)
+    pf_out = per_frame()
+    torch.cuda.synchronize()
+    k = 0
+    for i, w in enumerate(seqs):  # per-frame results are the batch's, bit for bit
+        for t in range(len(w.frames) - 1):
+            assert np.array_equal(acbm.to_numpy(pf_out[k]), res[i][t]), (i, t)
+            k += 1
+    p_ms, p_wall = timed(per_frame, 2)
+    evals = sum(int(r["cands"].astype(np.int64).sum()) * w.block_w * w.block_h
+                for r, w in zip(res, seqs))
+    gr.close()
+    return {"workload": "64 sequences x 8 frames: QCIF/CIF/1280x720/1920x1088, p 7/16/32, "
+                        "16x16 and 8x8 blocks, lambda 8, FSBM",
+            "pairs": sum(len(w.frames) - 1 for w in seqs), "evals": evals,
+            "graph_ms": g_ms, "graph_evals_per_s": evals / (g_ms / 1e3),
+            "graph_frac_of_peak": evals / (g_ms / 1e3) / (PEAK_TEVALS * 1e12),
+            "eager_batch_ms": e_ms, "per_frame_fsbm_ms": p_ms,
+            "per_frame_fsbm_wall_ms": p_wall,
+            "speedup_graph_vs_per_frame": p_ms / g_ms,
+            "tuned_rows": {f"{k[0]}x{k[1]}_p{k[2]}": v for k, v in tuned.items()}}
+
+
+def served_leg(acbm, synth, rates, seconds, nstreams=32, nfr=3):
+    """Poisson arrivals of frame-pair FSBM requests over 32 streams whose
+    resolution (640x480 .. 3840x2160) and p (16, 32, 64) are drawn per stream;
+    each stream cycles over nfr generated frames.  Latency is submit ->
+    result on the host (includes the frame upload and the result download)."""
+    specs = synth.serve_streams(nstreams)
+    frames = [synth.stream_frames(sp, nfr) for sp in specs]
+    out = {"workload": f"{nstreams} streams, 640x480..3840x2160, p 16/32/64, 16x16 blocks, "
+                       "lambda 8, FSBM, Poisson arrivals", "rates": {}}
+    for rate in rates:
+        n = max(1, int(rate * seconds))
+        times, sids = synth.serve_arrivals(rate, n, nstreams)
+        srv = acbm.Server(pool_bytes=24 << 30, max_streams=nstreams, max_inflight=4,
+                          queue_depth=8192)
+        try:
+            prm = acbm.default_params(16, 16, 8)
+            first = [srv.submit(s, frames[s][0], 16, 16, specs[s]["p"], prm, acbm.ALGO_FSBM)
+                     for s in range(nstreams)]
+            for t in first:
+                srv.wait(t)
+            nxt = [1] * nstreams
+            tickets, busy = [], 0
+            t0 = time.perf_counter()
+            for k in range(n):
+                target = t0 + float(times[k])
+                while True:
+                    now = time.perf_counter()
+                    if now >= target:
+                        break
+                    time.sleep(min(0.0005, target - now))
+                s = int(sids[k])
+                try:
+                    tickets.append(srv.submit(s, frames[s][nxt[s] % nfr], 16, 16, specs[s]["p"],
+                                              prm, acbm.ALGO_FSBM))
+                    nxt[s] += 1
+                except acbm.AcbmError as e:
+                    if e.status != acbm.E_BUSY:
+                        raise
+                    busy += 1
+            for t in tickets:
+                srv.wait(t)
+            t1 = time.perf_counter()
+            stt = srv.stats()
+        finally:
+            srv.close()
+        out["rates"][str(rate)] = {"offered_rps": rate, "requests": n, "completed": int(stt["completed"]),
+                                   "rejected_busy": busy, "achieved_rps": len(tickets) / (t1 - t0),
+                                   "p50_ms": stt["p50_us"] / 1e3, "p99_ms": stt["p99_us"] / 1e3,
+                                   "mean_ms": stt["mean_us"] / 1e3,
+                                   "gpu_busy_frac": stt["gpu_busy_frac"]}
+    return out
 
 
 def main():
@@ -111,6 +244,8 @@ def main():
 
     do_f = args.only in (None, "fsbm")
     do_a = args.only in (None, "acbm")
+    if args.only in ("batch", "serve"):
+        do_f = do_a = False
 
     def step(evs=None):
         if evs:
@@ -186,6 +321,10 @@ def main():
                            "unit": "T evals/s", "frac": achieved / PEAK_TEVALS, "traffic": None,
                            "kernel": "k_search (FSBM window search, QSAD)",
                            "launch_ms": search_ms / search_n}
+    if args.only in (None, "batch") and not args.no_batch:
+        out["batched"] = batched_leg(torch, acbm, synth, dev)
+    if args.only in (None, "serve") and not args.no_serve:
+        out["served"] = served_leg(acbm, synth, [200, 500, 1000, 2000], args.serve_seconds)
     if not args.no_cpu:
         import oracle
         out["cpu_baseline"] = cpu_baseline(wl, oracle.Params(lam=prm.lam, qp=prm.qp, alpha=prm.alpha,

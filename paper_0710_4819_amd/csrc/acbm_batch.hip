@@ -1,13 +1,13 @@
 // acbm_batch.hip -- many sequences of uneven geometry in one call.
 //
-// FSBM jobs (Section 2.3) are grouped by block size and window-search plan;
-// each group runs as one persistent full-search launch whose workgroups take
-// (job, pair, block) items from a counter, then one resolve launch with a
-// workgroup per pair of every job in the group.  The job tables those
-// launches read are written into the caller's workspace by small kernels
-// whose arguments carry the bytes, so the whole call is stream-ordered and
-// needs no host staging memory.  PBM/ACBM jobs (Sections 2.2, 3.2) keep
-// their own row-pipelined launch.
+// FSBM jobs (Section 2.3) are grouped by block size and window-search plan
+// (at most 64 jobs a group); each group runs as one full-search launch with
+// a workgroup per (job, pair, block) item, then a single resolve launch
+// takes every pair of every FSBM job at once.  The job tables those launches
+// read are written into the caller's workspace by small kernels whose
+// arguments carry the bytes, so the whole call is stream-ordered and needs
+// no host staging memory.  PBM/ACBM jobs (Sections 2.2, 3.2) keep their own
+// row-pipelined launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,8 +44,8 @@ struct Class {
   SearchPlan pl{};
   std::vector<BatchJob> jobs;
   std::vector<size_t> job_index;  // into the caller's job array
-  uint32_t items = 0, pairs = 0;
-  size_t lds_search = 0, lds_resolve = 0;
+  uint32_t items = 0;
+  size_t lds_search = 0;
 };
 
 struct Plan {
@@ -56,10 +56,12 @@ struct Plan {
   size_t table_off = 0, table_bytes = 0;
   size_t off_jobs = 0, off_ptrs = 0;  // within the table region
   size_t njob_fsbm = 0, nptr = 0;
+  uint32_t pairs = 0;             // FSBM pairs (resolve workgroups)
+  size_t lds_resolve = 0;
 };
 
 // Groups the jobs and lays out the workspace: job slices first, then the
-// table region [class counters][BatchJob per FSBM job][frame pointers].
+// table region [BatchJob per FSBM job][frame pointers].
 int make_plan(const acbm_job* jobs, size_t njobs, Plan* pl) {
   std::map<std::tuple<int, int, int, int>, size_t> cls;
   size_t off = 0;
@@ -81,6 +83,10 @@ int make_plan(const acbm_job* jobs, size_t njobs, Plan* pl) {
     if (!sp.R) return fail(ACBM_E_UNSUPPORTED, "search window does not fit in LDS");
     const auto key = std::make_tuple(k.bw, k.bh, sp.R, sp.threads);
     auto it = cls.find(key);
+    if (it != cls.end() && pl->classes[it->second].jobs.size() == 64) {
+      cls.erase(it);  // a full group: later jobs of this kind open a new one
+      it = cls.end();
+    }
     if (it == cls.end()) {
       it = cls.emplace(key, pl->classes.size()).first;
       pl->classes.emplace_back();
@@ -100,19 +106,23 @@ int make_plan(const acbm_job* jobs, size_t njobs, Plan* pl) {
     bj.lam = j.params.lambda;
     bj.npairs = npairs;
     bj.item0 = c.items;
-    bj.pair0 = c.pairs;
     c.items += npairs * (uint32_t)k.nb;
-    c.pairs += npairs;
     c.lds_search = std::max<size_t>(c.lds_search, (size_t)sp.lds_bytes);
-    if (fsbm_mv_in_lds(k)) c.lds_resolve = std::max<size_t>(c.lds_resolve, (size_t)k.nb * 4);
+    if (fsbm_mv_in_lds(k)) pl->lds_resolve = std::max<size_t>(pl->lds_resolve, (size_t)k.nb * 4);
     c.jobs.push_back(bj);
     c.job_index.push_back(i);
     pl->njob_fsbm += 1;
     pl->nptr += j.nframes;
   }
+  // resolve workgroups are numbered across all FSBM jobs, in table order
+  for (Class& c : pl->classes)
+    for (BatchJob& bj : c.jobs) {
+      bj.pair0 = pl->pairs;
+      pl->pairs += bj.npairs;
+    }
   pl->jobs_bytes = off;
   pl->table_off = off;
-  pl->off_jobs = align256(pl->classes.size() * sizeof(uint32_t));
+  pl->off_jobs = 0;
   pl->off_ptrs = pl->off_jobs + align256(pl->njob_fsbm * sizeof(BatchJob));
   pl->table_bytes = pl->classes.empty() ? 0 : pl->off_ptrs + align256(pl->nptr * sizeof(void*));
   return ACBM_OK;
@@ -133,7 +143,7 @@ __global__ void k_put_table(uint64_t* __restrict__ dst, const TableChunk c, int 
 int write_tables(const acbm_job* jobs, Plan* pl, char* ws, hipStream_t st) {
   if (!pl->table_bytes) return ACBM_OK;
   char* table = ws + pl->table_off;
-  std::vector<uint64_t> host(pl->table_bytes / 8, 0);  // counters start at zero
+  std::vector<uint64_t> host(pl->table_bytes / 8, 0);
   char* hb = reinterpret_cast<char*>(host.data());
   size_t jo = 0, po = 0;
   for (Class& c : pl->classes) {
@@ -211,18 +221,15 @@ int enqueue_batch(const acbm_job* jobs, size_t njobs, void* ws, hipStream_t st) 
   if (rc) return rc;
   char* base = static_cast<char*>(ws);
   if ((rc = write_tables(jobs, &pl, base, st))) return rc;
+  const BatchJob* all = reinterpret_cast<const BatchJob*>(base + pl.table_off + pl.off_jobs);
   size_t jo = 0;
-  for (size_t ci = 0; ci < pl.classes.size(); ++ci) {
-    const Class& c = pl.classes[ci];
-    const BatchJob* dj =
-        reinterpret_cast<const BatchJob*>(base + pl.table_off + pl.off_jobs + jo * sizeof(BatchJob));
-    uint32_t* counter = reinterpret_cast<uint32_t*>(base + pl.table_off) + ci;
-    rc = launch_search_batch(c.N, c.M, c.pl, c.lds_search, dj, (int)c.jobs.size(), c.items,
-                             counter, st);
-    if (!rc) rc = launch_resolve_batch(dj, (int)c.jobs.size(), c.pairs, c.lds_resolve, st);
+  for (const Class& c : pl.classes) {
+    rc = launch_search_batch(c.N, c.M, c.pl, c.lds_search, all + jo, (int)c.jobs.size(), c.items,
+                             st);
     if (rc) return rc;
     jo += c.jobs.size();
   }
+  if ((rc = launch_resolve_batch(all, (int)pl.njob_fsbm, pl.pairs, pl.lds_resolve, st))) return rc;
   for (size_t i : pl.predictive) {
     const acbm_job& j = jobs[i];
     KGeom k;

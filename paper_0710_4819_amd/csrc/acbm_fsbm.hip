@@ -26,6 +26,13 @@
 
 namespace acbm {
 
+// Overflow rows hold (2p+1)^2 u16 SADs padded to a multiple of 8 entries,
+// so that every row starts 16-byte aligned and can be read in uint4 pieces.
+__host__ __device__ __forceinline__ size_t ovf_stride(int p) {
+  const size_t ww = (size_t)(2 * p + 1) * (2 * p + 1);
+  return (ww + 7) & ~(size_t)7;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs.  Remap so that each
 // XCD gets one contiguous band of blocks: neighbouring blocks share most of
 // their search windows, and a band then stays in one XCD's L2.
@@ -175,51 +182,36 @@ k_search(const KGeom g, const WindowShape s, const FramePtrs fr, uint32_t* __res
   const size_t at = (size_t)pair * g.nb + b;
   search_block<N, M, R, kTable>(g, s, fr.f[pair], fr.f[pair + 1], b,
                                 kTable ? table + (size_t)b * WW : nullptr,
-                                kTable ? nullptr : recs + at, kTable ? nullptr : ovf + at * WW,
+                                kTable ? nullptr : recs + at,
+                                kTable ? nullptr : ovf + at * ovf_stride(s.p),
                                 slack, win, red, &n_keep);
 }
 
-// Persistent full search over the jobs of one batch class: workgroups take
-// (job, pair, block) items from one counter until none are left.
+// Full search over the jobs of one batch group: one workgroup per
+// (job, pair, block) item, items numbered job by job (pair-major within a
+// job) and handed out in one contiguous band per XCD like k_search.  The
+// job of an item is found with one load per lane (lane k reads job k's
+// first item) and a ballot, so a group of up to 64 jobs costs one memory
+// round trip.
 template <int N, int M, int R>
 __global__ void __launch_bounds__(1024)
-k_search_batch(const BatchJob* __restrict__ jobs, int njobs, uint32_t items,
-               uint32_t* __restrict__ counter) {
+k_search_batch(const BatchJob* __restrict__ jobs, int njobs, uint32_t items) {
   extern __shared__ uint32_t win[];
   __shared__ uint64_t red[16];
-  __shared__ uint32_t n_keep, sh_item;
-  // Item fetch: thread 0 takes the next item, a barrier publishes it, and
-  // readfirstlane makes it wave-uniform for the compiler.  Every iteration
-  // ends with a barrier before the next fetch, so no thread-0-only region
-  // spans the loop's back edge: otherwise the control-flow structurizer may
-  // turn the loop (which contains barriers) into a nest in which the lanes
-  // other than thread 0 re-run the same item and never exit.
-  if (threadIdx.x == 0) sh_item = atomicAdd(counter, 1u);
-  __syncthreads();
-  uint32_t it = __builtin_amdgcn_readfirstlane(sh_item);
-  while (it < items) {
-    int j = 0;
-    while (j + 1 < njobs && jobs[j + 1].item0 <= it) ++j;
-    j = __builtin_amdgcn_readfirstlane(j);
-    const BatchJob& J = jobs[j];
-    const KGeom g = J.g;
-    const uint32_t local = it - J.item0;
-    const int pair = (int)(local / (uint32_t)g.nb), b = (int)(local % (uint32_t)g.nb);
-    const size_t WW = (size_t)(2 * g.p + 1) * (2 * g.p + 1);
-    const size_t at = (size_t)pair * g.nb + b;
-    search_block<N, M, R, false>(g, J.s, J.frames[pair], J.frames[pair + 1], b, nullptr,
-                                 J.recs + at, J.ovf + at * WW, J.slack, win, red, &n_keep);
-    __syncthreads();
-    if (threadIdx.x == 0) sh_item = atomicAdd(counter, 1u);
-    __syncthreads();
-    it = __builtin_amdgcn_readfirstlane(sh_item);
-  }
-}
-
-// Sets n counters to zero (a kernel, so that it can sit in a graph).
-__global__ void k_zero_u32(uint32_t* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
+  __shared__ uint32_t n_keep;
+  const uint32_t it = (uint32_t)xcd_band(blockIdx.x, (int)items);
+  if (it >= items) return;
+  const int lane = threadIdx.x & 63;
+  const uint32_t first = lane < njobs ? jobs[lane].item0 : 0xFFFFFFFFu;
+  const int j = __builtin_amdgcn_readfirstlane(__popcll(__ballot(first <= it)) - 1);
+  const BatchJob& J = jobs[j];
+  const KGeom g = J.g;
+  const uint32_t local = it - J.item0;
+  const int pair = (int)(local / (uint32_t)g.nb), b = (int)(local % (uint32_t)g.nb);
+  const size_t at = (size_t)pair * g.nb + b;
+  search_block<N, M, R, false>(g, J.s, J.frames[pair], J.frames[pair + 1], b, nullptr,
+                               J.recs + at, J.ovf + at * ovf_stride(g.p), J.slack, win, red,
+                               &n_keep);
 }
 
 // ---------------------------------------------------------------------------
@@ -277,15 +269,42 @@ __device__ __forceinline__ uint64_t wave_block_argmin(const BlockRec* __restrict
       best = make_key(j, u, v, p);
     }
   } else {
-    const int WW = (2 * p + 1) * (2 * p + 1);
-    for (int ras = lane; ras < WW; ras += 64) {
-      const uint32_t sad = row[ras];
-      if (sad == 0xFFFFu) continue;
-      int u, v;
-      window_uv((uint32_t)ras, p, &u, &v);
-      const uint32_t j = sad + lam * (se_bits(u - px) + se_bits(v - py));
-      const uint64_t key = make_key(j, u, v, p);
-      best = key < best ? key : best;
+    // The whole row, read as uint4 pieces of 8 SADs: lane k takes pieces
+    // k, k+64, ...; up to kPieces of them are loaded before any is used, so
+    // the row costs about one memory latency.
+    const int W = 2 * p + 1, WW = W * W;
+    const int npieces = (WW + 7) / 8;
+    const uint4* __restrict__ row4 = reinterpret_cast<const uint4*>(row);
+    constexpr int kPieces = 9;  // 9 * 64 * 8 = 4608 >= (2*32+1)^2
+    for (int c0 = lane; c0 < npieces; c0 += 64 * kPieces) {
+      uint4 q[kPieces];
+#pragma unroll
+      for (int k = 0; k < kPieces; ++k) {
+        const int c = c0 + 64 * k;
+        q[k] = c < npieces ? row4[c] : make_uint4(~0u, ~0u, ~0u, ~0u);
+      }
+#pragma unroll
+      for (int k = 0; k < kPieces; ++k) {
+        const int c = c0 + 64 * k;
+        if (c >= npieces) break;
+        const int pos = 8 * c;
+        int u = pos % W - p, v = pos / W - p;
+        const uint32_t w4[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t sad = (w4[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+          if (sad != 0xFFFFu && pos + e < WW) {
+            const uint32_t j = sad + lam * (se_bits(u - px) + se_bits(v - py));
+            const uint64_t key =
+                ((uint64_t)j << 32) | ((uint32_t)(abs(u) + abs(v)) << 16) | (uint32_t)(pos + e);
+            best = key < best ? key : best;
+          }
+          if (++u > p) {
+            u = -p;
+            ++v;
+          }
+        }
+      }
     }
   }
   return wave_min_u64(best);
@@ -337,7 +356,7 @@ __device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __r
         const int bb = base + k;
         const int qx = __shfl(px, k, 64), qy = __shfl(py, k, 64);
         const uint64_t key =
-            wave_block_argmin(recs + bb, ovf + (size_t)bb * (W * W), p, qx, qy, lam);
+            wave_block_argmin(recs + bb, ovf + (size_t)bb * ovf_stride(p), p, qx, qy, lam);
         int u = 0, v = 0;
         uint32_t sad = 0;
         if (key != ~0ull) {
@@ -385,8 +404,7 @@ k_resolve(const KGeom g, const BlockRec* __restrict__ recs, const uint16_t* __re
   extern __shared__ uint32_t st_lds[];
   __shared__ int pending;
   const int pair = blockIdx.x;
-  const size_t WW = (size_t)(2 * g.p + 1) * (2 * g.p + 1);
-  resolve_pair(g, recs + (size_t)pair * g.nb, ovf + (size_t)pair * g.nb * WW,
+  resolve_pair(g, recs + (size_t)pair * g.nb, ovf + (size_t)pair * g.nb * ovf_stride(g.p),
                out + (size_t)pair * g.nb, lam,
                st_global ? st_global + (size_t)pair * g.nb : st_lds, &pending);
 }
@@ -398,13 +416,18 @@ k_resolve_batch(const BatchJob* __restrict__ jobs, int njobs) {
   __shared__ int pending;
   const uint32_t wg = blockIdx.x;
   int j = 0;
-  while (j + 1 < njobs && jobs[j + 1].pair0 <= wg) ++j;
+  for (int base = 0; base < njobs; base += 64) {  // jobs are sorted by pair0
+    const int k = base + (int)(threadIdx.x & 63);
+    const uint32_t first = k < njobs ? jobs[k].pair0 : 0xFFFFFFFFu;
+    const int n = __popcll(__ballot(first <= wg));
+    if (n == 0) break;
+    j = base + n - 1;
+  }
   j = __builtin_amdgcn_readfirstlane(j);  // uniform: the resolve loops contain barriers
   const BatchJob& J = jobs[j];
   const KGeom g = J.g;
   const int pair = (int)(wg - J.pair0);
-  const size_t WW = (size_t)(2 * g.p + 1) * (2 * g.p + 1);
-  resolve_pair(g, J.recs + (size_t)pair * g.nb, J.ovf + (size_t)pair * g.nb * WW,
+  resolve_pair(g, J.recs + (size_t)pair * g.nb, J.ovf + (size_t)pair * g.nb * ovf_stride(g.p),
                J.out + (size_t)pair * g.nb, J.lam,
                J.mv_ws ? J.mv_ws + (size_t)pair * g.nb : st_lds, &pending);
 }
@@ -473,37 +496,21 @@ int launch_search_plan(const KGeom& g, const SearchPlan& pl, const uint8_t* cons
   return launch_search_with<false>(g, pl, fr, npairs, nullptr, recs, ovf, slack, st);
 }
 
-// Persistent batch kernels ---------------------------------------------------
-static int device_cus() {
-  static int cus = 0;
-  if (!cus) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 256;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      cus = 256;
-  }
-  return cus;
-}
-
+// Batch kernels ---------------------------------------------------------------
 template <int N, int M>
 static int launch_search_batch_nm(const SearchPlan& pl, size_t lds, const BatchJob* jobs,
-                                  int njobs, uint32_t items, uint32_t* counter, hipStream_t st) {
+                                  int njobs, uint32_t items, hipStream_t st) {
+  const int grid = (int)(((uint64_t)items + 7) / 8 * 8);
   switch (pl.R) {
-#define ACBM_CASE(RR)                                                                         \
-  case RR: {                                                                                  \
-    const void* fn = (const void*)k_search_batch<N, M, RR>;                                   \
-    if (lds > 64 * 1024)                                                                      \
-      (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);    \
-    int per_cu = 0;                                                                           \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, pl.threads, lds) !=         \
-            hipSuccess ||                                                                     \
-        per_cu < 1)                                                                           \
-      per_cu = 1;                                                                             \
-    const int grid = (int)std::min<uint64_t>((uint64_t)device_cus() * per_cu, items);         \
-    ProfScope ps("search", st);                                                               \
-    hipLaunchKernelGGL((k_search_batch<N, M, RR>), dim3(grid), dim3(pl.threads), lds, st,     \
-                       jobs, njobs, items, counter);                                          \
-    break;                                                                                    \
+#define ACBM_CASE(RR)                                                                      \
+  case RR: {                                                                               \
+    if (lds > 64 * 1024)                                                                   \
+      (void)hipFuncSetAttribute((const void*)k_search_batch<N, M, RR>,                     \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);     \
+    ProfScope ps("search", st);                                                            \
+    hipLaunchKernelGGL((k_search_batch<N, M, RR>), dim3(grid), dim3(pl.threads), lds, st,  \
+                       jobs, njobs, items);                                                \
+    break;                                                                                 \
   }
     ACBM_R_LIST(ACBM_CASE)
 #undef ACBM_CASE
@@ -515,30 +522,28 @@ static int launch_search_batch_nm(const SearchPlan& pl, size_t lds, const BatchJ
 }
 
 int launch_search_batch(int N, int M, const SearchPlan& pl, size_t lds, const BatchJob* jobs,
-                        int njobs, uint32_t items, uint32_t* counter, hipStream_t st) {
+                        int njobs, uint32_t items, hipStream_t st) {
   if (!items) return ACBM_OK;
-  if (N == 16 && M == 16) return launch_search_batch_nm<16, 16>(pl, lds, jobs, njobs, items, counter, st);
-  if (N == 16 && M == 8) return launch_search_batch_nm<16, 8>(pl, lds, jobs, njobs, items, counter, st);
-  if (N == 8 && M == 16) return launch_search_batch_nm<8, 16>(pl, lds, jobs, njobs, items, counter, st);
-  if (N == 8 && M == 8) return launch_search_batch_nm<8, 8>(pl, lds, jobs, njobs, items, counter, st);
+  if (njobs > 64) return fail(ACBM_E_INVAL, "more than 64 jobs in one search group");
+  if (N == 16 && M == 16) return launch_search_batch_nm<16, 16>(pl, lds, jobs, njobs, items, st);
+  if (N == 16 && M == 8) return launch_search_batch_nm<16, 8>(pl, lds, jobs, njobs, items, st);
+  if (N == 8 && M == 16) return launch_search_batch_nm<8, 16>(pl, lds, jobs, njobs, items, st);
+  if (N == 8 && M == 8) return launch_search_batch_nm<8, 8>(pl, lds, jobs, njobs, items, st);
   return fail(ACBM_E_UNSUPPORTED, "block size must be 8 or 16 in each direction");
 }
 
 int launch_resolve_batch(const BatchJob* jobs, int njobs, uint32_t pairs, size_t lds,
                          hipStream_t st) {
   if (!pairs) return ACBM_OK;
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)k_resolve_batch,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   ProfScope ps("resolve", st);
   hipLaunchKernelGGL(k_resolve_batch, dim3(pairs), dim3(1024), lds, st, jobs, njobs);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? ACBM_OK : hip_fail(e, "launching the batched resolve");
 }
 
-int launch_zero_u32(uint32_t* p, int n, hipStream_t st) {
-  if (n <= 0) return ACBM_OK;
-  hipLaunchKernelGGL(k_zero_u32, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
-  hipError_t e = hipGetLastError();
-  return e == hipSuccess ? ACBM_OK : hip_fail(e, "launching a counter reset");
-}
 
 int launch_sad_table(const KGeom& g, const uint8_t* cur, const uint8_t* ref, uint32_t* table,
                      hipStream_t st) {
@@ -548,13 +553,12 @@ int launch_sad_table(const KGeom& g, const uint8_t* cur, const uint8_t* ref, uin
   return launch_search<true>(g, fr, 1, table, nullptr, nullptr, 0, st);
 }
 
-static size_t ovf_row_bytes(const KGeom& g) {
-  const size_t W = 2 * (size_t)g.p + 1;
-  return W * W * sizeof(uint16_t);
-}
+static size_t ovf_row_bytes(const KGeom& g) { return ovf_stride(g.p) * sizeof(uint16_t); }
 
-// State of the resolve kernel stays in LDS up to this many bytes.
-constexpr size_t kResolveLdsMax = 48 * 1024;
+// State of the resolve kernel stays in LDS up to this many bytes (of the
+// 160 KiB a workgroup can have on gfx950): up to 36864 blocks, e.g. 8x8
+// blocks of 1920x1088 or 16x16 blocks of 3840x2160.
+constexpr size_t kResolveLdsMax = 144 * 1024;
 
 size_t fsbm_recs_offset() { return align256(sizeof(WsHeader)); }
 size_t fsbm_ovf_offset(const KGeom& g, uint32_t npairs) {
@@ -597,9 +601,12 @@ int launch_fsbm(const KGeom& g, const acbm_params& prm, const uint8_t* const* fr
     uint16_t* o = ovf + (size_t)p0 * g.nb * (ovf_row_bytes(g) / 2);
     int rc = launch_search<false>(g, fr, n, nullptr, r, o, slack, st);
     if (rc) return rc;
+    const size_t rlds = mv_in_lds ? (size_t)g.nb * sizeof(uint32_t) : 0;
+    if (rlds > 64 * 1024)
+      (void)hipFuncSetAttribute((const void*)k_resolve, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)rlds);
     ProfScope ps("resolve", st);
-    hipLaunchKernelGGL(k_resolve, dim3(n), dim3(1024),
-                       mv_in_lds ? (size_t)g.nb * sizeof(uint32_t) : 0, st, g, r, o,
+    hipLaunchKernelGGL(k_resolve, dim3(n), dim3(1024), rlds, st, g, r, o,
                        out + (size_t)p0 * g.nb, prm.lambda,
                        mv_in_lds ? nullptr : mv_ws + (size_t)p0 * g.nb);
     hipError_t e = hipGetLastError();

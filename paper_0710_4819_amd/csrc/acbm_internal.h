@@ -49,9 +49,10 @@ struct WindowShape {
   int stride;  // LDS row stride in dwords
 };
 
-// One FSBM job of a batch class as the persistent batch kernels read it
-// (device memory).  Search items are (pair, block) in pair-major order,
-// numbered from item0 within the class; resolve workgroups from pair0.
+// One FSBM job of a batch as the batch kernels read it (device memory).
+// Search items are (pair, block) in pair-major order, numbered from item0
+// within the job's search group; resolve workgroups, one per pair, are
+// numbered from pair0 across all FSBM jobs of the batch.
 struct BatchJob {
   KGeom g;
   WindowShape s;
@@ -134,12 +135,13 @@ size_t fsbm_recs_offset();                    // BlockRec array offset in an FSB
 size_t fsbm_ovf_offset(const KGeom& g, uint32_t npairs);
 size_t fsbm_mv_offset(const KGeom& g, uint32_t npairs);  // resolve state, if used
 bool fsbm_mv_in_lds(const KGeom& g);
-// Persistent kernels of one batch class (jobs with the same N, M and plan).
+// Batch kernels: the full search of one group (at most 64 jobs with the
+// same N, M and plan; one workgroup per item) and the resolve of every pair
+// of a set of FSBM jobs (one workgroup per pair).
 int launch_search_batch(int N, int M, const SearchPlan& pl, size_t lds, const BatchJob* jobs,
-                        int njobs, uint32_t items, uint32_t* counter, hipStream_t s);
+                        int njobs, uint32_t items, hipStream_t s);
 int launch_resolve_batch(const BatchJob* jobs, int njobs, uint32_t pairs, size_t lds,
                          hipStream_t s);
-int launch_zero_u32(uint32_t* p, int n, hipStream_t s);
 size_t predictive_ws_bytes(const KGeom& g, uint32_t npairs);
 int launch_predictive(const KGeom& g, const acbm_params& prm, int algo,
                       const uint8_t* const* frames, uint32_t npairs, const acbm_mv* prev_field,
