@@ -32,6 +32,11 @@ __host__ __device__ __forceinline__ size_t ovf_stride(int p) {
   const size_t ww = (size_t)(2 * p + 1) * (2 * p + 1);
   return (ww + 7) & ~(size_t)7;
 }
+// The same region holds, when a block has more than kShort but at most this
+// many possible winners, their full list as u32 (SAD << 16 | raster index).
+__host__ __device__ __forceinline__ uint32_t ovf_list_cap(int p) {
+  return (uint32_t)(ovf_stride(p) / 2);
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs.  Remap so that each
 // XCD gets one contiguous band of blocks: neighbouring blocks share most of
@@ -67,9 +72,12 @@ __device__ __forceinline__ uint32_t wave_intra_x(const uint8_t* __restrict__ cur
 
 // ---------------------------------------------------------------------------
 // Window search of one block (all threads of the group).  kTable: write the
-// block's u32 table `tab`; else write its BlockRec `rec` and, when more than
-// kShort candidates can win, its overflow row `row`.  `win` is the window
-// in LDS, `red` one slot per wave, `n_keep` a shared counter.
+// block's u32 table `tab`; else write its BlockRec `rec` (SAD minimum, the
+// number of candidates that can still win and the first kShort of them) and,
+// when more than kShort can win, its overflow region `row`: the list of all
+// of them while it fits (ovf_list_cap entries), else the whole row of SADs.
+// `win` is the window in LDS, `red` one slot per wave, `n_keep` a shared
+// counter.
 // ---------------------------------------------------------------------------
 template <int N, int M, int R, bool kTable>
 __device__ __forceinline__ void search_block(const KGeom& g, const WindowShape& s,
@@ -133,21 +141,26 @@ __device__ __forceinline__ void search_block(const KGeom& g, const WindowShape& 
 #pragma unroll
       for (int i = 0; i < 4; ++i) mine += ((uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu) <= thr;
     uint32_t slot = atomicAdd(n_keep, mine);
+    const uint32_t cap = ovf_list_cap(p);
+    uint32_t* __restrict__ list = reinterpret_cast<uint32_t*>(row);
 #pragma unroll
     for (int rr = 0; rr < R; ++rr)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const uint32_t sad = (uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu;
         if (sad <= thr) {
-          if (slot < (uint32_t)kShort)
-            rec->e[slot] = (sad << 16) | (uint32_t)((v0 + rr + p) * W + (u0 + i + p));
+          const uint32_t e = (sad << 16) | (uint32_t)((v0 + rr + p) * W + (u0 + i + p));
+          if (slot < (uint32_t)kShort) rec->e[slot] = e;
+          if (slot < cap) list[slot] = e;  // used when kShort < total <= cap
           ++slot;
         }
       }
   }
   __syncthreads();
   const uint32_t total = *n_keep;
-  if (total > (uint32_t)kShort && active) {
+  // more candidates than the list holds: the whole row of SADs instead
+  // (written after the barrier, so it replaces any list entries)
+  if (total > ovf_list_cap(p) && active) {
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
       const int v = v0 + rr;
@@ -260,7 +273,22 @@ __device__ __forceinline__ uint64_t wave_block_argmin(const BlockRec* __restrict
   const uint32_t w = lane < 32 ? reinterpret_cast<const uint32_t*>(rec)[lane] : 0u;
   const uint32_t n = (uint32_t)__shfl((int)w, 1, 64);  // rec->count
   uint64_t best = ~0ull;
-  if (n <= (uint32_t)kShort) {
+  if (n > (uint32_t)kShort && n <= ovf_list_cap(p)) {
+    // the full list of possible winners; v = ras / W by an exact
+    // multiply-high with ceil(2^32 / W) (ras < 2^16, W < 2^8)
+    const uint32_t W = 2u * (uint32_t)p + 1u;
+    const uint32_t inv = (uint32_t)(((1ull << 32) + W - 1) / W);
+    const uint32_t* __restrict__ list = reinterpret_cast<const uint32_t*>(row);
+    for (uint32_t k = (uint32_t)lane; k < n; k += 64) {
+      const uint32_t e = list[k];
+      const uint32_t ras = e & 0xFFFFu;
+      const uint32_t vq = __umulhi(ras, inv);
+      const int v = (int)vq - p, u = (int)(ras - vq * W) - p;
+      const uint32_t j = (e >> 16) + lam * (se_bits(u - px) + se_bits(v - py));
+      const uint64_t key = ((uint64_t)j << 32) | ((uint32_t)(abs(u) + abs(v)) << 16) | ras;
+      best = key < best ? key : best;
+    }
+  } else if (n <= (uint32_t)kShort) {
     const int k = lane - 4;  // e[k] is dword 4 + k of the record
     if (k >= 0 && k < (int)n) {
       int u, v;

@@ -105,6 +105,11 @@ def search_cases():
     yield "tex_8x16_p11_l3", c, r, 8, 16, 11, 3, None
     sc = synth.cif_scene(nframes=2, lam=32)
     yield "cif_scene_p16_l32", sc.frames[1], sc.frames[0], 16, 16, 16, 32, None
+    # smooth texture, small blocks, large lambda: many blocks have more than
+    # the record's kShort possible winners but fewer than a whole row
+    ref = synth.texture(64, 96, 6.0, synth.rng(24))
+    cur = synth.add_noise(np.roll(ref, (1, 2), (0, 1)), 1.0, synth.rng(25))
+    yield "smooth_8x8_p16_l32", cur, ref, 8, 8, 16, 32, None
 
 
 @pytest.mark.parametrize("case", list(search_cases()), ids=lambda c: c[0])
