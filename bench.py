@@ -41,6 +41,25 @@ METRIC = "candidate-pixel SAD evals/s + 1080p p=32 frames/s (FSBM vs ACBM), % VA
 PEAK_TEVALS = 256 * 64 * 2.4e9 * 4 / 1e12
 
 
+# HBM bytes per launch of the FSBM window search on the 1920x1088 p = 32
+# sequence (59 pairs), from two rocprofv3 --pmc runs of
+# `bench.py --steps 1 --warmup 0 --no-cpu --only fsbm --calib-copy-mib 256`:
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of k_search<16,16,6,false>,
+# each scaled by what the same counter reads for the 256 MiB device copy in
+# that run (FETCH_SIZE reads 131090.6 KiB for 262144 KiB moved, WRITE_SIZE
+# 262144 KiB).  Valid for the kernel these counters were taken on; set to
+# None when the search kernel changes.
+SEARCH_TRAFFIC = {"kernel": "k_search<16,16,6,false>", "fetch_kib": 147181.9,
+                  "write_kib": 31368.5, "fetch_scale": 262144.0 / 131090.6, "write_scale": 1.0}
+
+
+def search_traffic_bytes():
+    t = SEARCH_TRAFFIC
+    if t is None:
+        return None
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,7 +183,7 @@ def served_leg(acbm, synth, rates, seconds, nstreams=32, nfr=3):
     for rate in rates:
         n = max(1, int(rate * seconds))
         times, sids = synth.serve_arrivals(rate, n, nstreams)
-        srv = acbm.Server(pool_bytes=24 << 30, max_streams=nstreams, max_inflight=4,
+        srv = acbm.Server(pool_bytes=24 << 30, max_streams=nstreams, max_inflight=16,
                           queue_depth=8192)
         try:
             prm = acbm.default_params(16, 16, 8)
@@ -317,8 +336,12 @@ def main():
     if do_f and search_n:
         per_launch = ev_f / (search_n / args.steps)  # one search launch covers all 59 pairs
         achieved = per_launch / (search_ms / search_n / 1e3) / 1e12
+        traffic = search_traffic_bytes()
         out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_TEVALS,
-                           "unit": "T evals/s", "frac": achieved / PEAK_TEVALS, "traffic": None,
+                           "unit": "T evals/s", "frac": achieved / PEAK_TEVALS, "traffic": traffic,
+                           "traffic_unit": "HBM bytes per launch",
+                           "traffic_GBps": (traffic / (search_ms / search_n / 1e3) / 1e9
+                                            if traffic else None),
                            "kernel": "k_search (FSBM window search, QSAD)",
                            "launch_ms": search_ms / search_n}
     if args.only in (None, "batch") and not args.no_batch:

@@ -224,8 +224,20 @@ int enqueue_batch(const acbm_job* jobs, size_t njobs, void* ws, hipStream_t st) 
   const BatchJob* all = reinterpret_cast<const BatchJob*>(base + pl.table_off + pl.off_jobs);
   size_t jo = 0;
   for (const Class& c : pl.classes) {
-    rc = launch_search_batch(c.N, c.M, c.pl, c.lds_search, all + jo, (int)c.jobs.size(), c.items,
-                             st);
+    const acbm_job& j0 = jobs[c.job_index[0]];
+    if (c.jobs.size() == 1 && j0.nframes - 1 <= (uint32_t)kMaxPairsPerLaunch) {
+      // a group of one job: the plain per-block search reads its frame
+      // pointers from kernel arguments, without the job-table lookup
+      const BatchJob& bj = c.jobs[0];
+      char* sl = base + pl.slice[c.job_index[0]];
+      rc = launch_search_plan(bj.g, c.pl, j0.frames, (int)bj.npairs,
+                              reinterpret_cast<BlockRec*>(sl + fsbm_recs_offset()),
+                              reinterpret_cast<uint16_t*>(sl + fsbm_ovf_offset(bj.g, bj.npairs)),
+                              bj.slack, st);
+    } else {
+      rc = launch_search_batch(c.N, c.M, c.pl, c.lds_search, all + jo, (int)c.jobs.size(),
+                               c.items, st);
+    }
     if (rc) return rc;
     jo += c.jobs.size();
   }
