@@ -105,6 +105,15 @@ typedef struct acbm_block_result {
     uint64_t intra_x;    /* N*M*Intra_SAD (exact; Section 3.1)              */
 } acbm_block_result;
 
+/* Block statistics of Section 3.1, 32 bytes per block, row-major [by][bx]. */
+typedef struct acbm_block_stats {
+    uint32_t sad_min;        /* smallest SAD over the valid window            */
+    uint32_t valid;          /* number of valid candidates (the window)       */
+    uint64_t sad_deviation;  /* sum over the valid window of SAD - sad_min    */
+    uint64_t intra_x;        /* N*M*Intra_SAD (exact)                         */
+    uint64_t reserved;       /* written as 0                                  */
+} acbm_block_stats;
+
 /* ---- library ------------------------------------------------------------ */
 const char* acbm_version(void);
 const char* acbm_strerror(int status);
@@ -128,6 +137,15 @@ int acbm_workspace_status(const void* ws, size_t ws_bytes, void* stream, int* st
  * (u,v), or 0xFFFFFFFF where (u,v) is not a valid candidate.  No workspace. */
 int acbm_sad_table(const acbm_geom* g, const uint8_t* cur, const uint8_t* ref,
                    uint32_t* table, void* stream);
+
+/* Block statistics of one frame pair (Section 3.1, Intra_SAD and
+ * SAD_deviation equations): for every block, over its full valid window,
+ * SAD_min, the number of valid positions, SAD_deviation = sum of
+ * |SAD(u,v) - SAD_min| (every term is >= 0) and IntraX = N*M*Intra_SAD.
+ * out is caller-owned device memory of by*bx records.  No workspace, no
+ * allocation; asynchronous on `stream`.  Errors: as acbm_sad_table. */
+int acbm_sad_stats(const acbm_geom* g, const uint8_t* cur, const uint8_t* ref,
+                   acbm_block_stats* out, void* stream);
 
 /* FSBM for one frame pair (Section 2.3 with the cost of Section 2.1):
  * out[r][c] = the minimum of J over the valid window; cands = number of valid
@@ -220,8 +238,9 @@ int acbm_autotune(const acbm_geom* g, uint32_t* best_rows, float* best_ms, void*
  * on the stream it runs on.  acbm_profile_read waits for the recorded events
  * and returns the summed device time and the launch count of one kernel
  * since the last reset.  Kernel names: "search" (window search, all block
- * sizes), "resolve" (FSBM argmin), "predictive" (PBM/ACBM), "setup"
- * (predictive workspace set-up), "field" (served field extraction). */
+ * sizes), "stats" (block statistics), "resolve" (FSBM argmin), "predictive"
+ * (PBM/ACBM), "setup" (predictive workspace set-up), "field" (served field
+ * extraction). */
 int acbm_profile_enable(int on);
 int acbm_profile_reset(void);
 int acbm_profile_read(const char* kernel, double* total_ms, uint64_t* launches);

@@ -38,6 +38,13 @@ RESULT_DTYPE = np.dtype({
     "itemsize": 32,
 })
 
+STATS_DTYPE = np.dtype({
+    "names": ["sad_min", "valid", "sad_deviation", "intra_x"],
+    "formats": ["<u4", "<u4", "<u8", "<u8"],
+    "offsets": [0, 4, 8, 16],
+    "itemsize": 32,
+})
+
 
 class Geom(C.Structure):
     _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("pitch", C.c_uint32),
@@ -112,6 +119,7 @@ def lib():
         L.acbm_workspace_size.argtypes = [C.c_int, P(Geom), C.c_uint32, P(sz)]
         L.acbm_workspace_status.argtypes = [vp, sz, vp, P(C.c_int)]
         L.acbm_sad_table.argtypes = [P(Geom), vp, vp, vp, vp]
+        L.acbm_sad_stats.argtypes = [P(Geom), vp, vp, vp, vp]
         L.acbm_fsbm_frame.argtypes = [P(Geom), P(CParams), vp, vp, vp, vp, sz, vp]
         L.acbm_pbm_frame.argtypes = [P(Geom), P(CParams), vp, vp, vp, vp, vp, sz, vp]
         L.acbm_acbm_frame.argtypes = [P(Geom), P(CParams), vp, vp, vp, vp, vp, sz, vp]
@@ -191,6 +199,17 @@ def sad_table(cur, ref, block_w, block_h, p, width=None, stream=None) -> torch.T
     W = 2 * p + 1
     out = torch.empty((by, bx, W, W), dtype=torch.int32, device=cur.device)
     _check(lib().acbm_sad_table(C.byref(g), cur.data_ptr(), ref.data_ptr(), out.data_ptr(),
+                                _stream(stream)))
+    return out
+
+
+def sad_stats(cur, ref, block_w, block_h, p, width=None, stream=None) -> torch.Tensor:
+    """Per-block SAD_min, valid count, SAD_deviation and IntraX
+    (acbm_block_stats records, [by, bx, 32] bytes; see stats_to_numpy)."""
+    g = geom(cur, block_w, block_h, p, width)
+    by, bx = _blocks(g)
+    out = torch.empty((by, bx, 32), dtype=torch.uint8, device=cur.device)
+    _check(lib().acbm_sad_stats(C.byref(g), cur.data_ptr(), ref.data_ptr(), out.data_ptr(),
                                 _stream(stream)))
     return out
 
@@ -381,3 +400,8 @@ def to_numpy(res: torch.Tensor) -> np.ndarray:
 
 def table_to_numpy(t: torch.Tensor) -> np.ndarray:
     return t.detach().cpu().numpy().view(np.uint32)
+
+
+def stats_to_numpy(st: torch.Tensor) -> np.ndarray:
+    a = st.detach().cpu().contiguous().numpy()
+    return a.view(STATS_DTYPE).reshape(a.shape[:-1])

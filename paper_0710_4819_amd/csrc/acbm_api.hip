@@ -271,6 +271,17 @@ int acbm_sad_table(const acbm_geom* g, const uint8_t* cur, const uint8_t* ref, u
   return launch_sad_table(k, cur, ref, table, static_cast<hipStream_t>(stream));
 }
 
+int acbm_sad_stats(const acbm_geom* g, const uint8_t* cur, const uint8_t* ref,
+                   acbm_block_stats* out, void* stream) {
+  KGeom k;
+  int rc = check_geom(g, &k);
+  if (rc) return rc;
+  if ((rc = check_frame_ptr(cur, "cur")) || (rc = check_frame_ptr(ref, "ref"))) return rc;
+  if (!out) return fail(ACBM_E_INVAL, "out is NULL");
+  if ((rc = check_device())) return rc;
+  return launch_sad_stats(k, cur, ref, out, static_cast<hipStream_t>(stream));
+}
+
 int acbm_fsbm_frame(const acbm_geom* g, const acbm_params* prm, const uint8_t* cur,
                     const uint8_t* ref, acbm_block_result* out, void* ws, size_t ws_bytes,
                     void* stream) {

@@ -71,21 +71,30 @@ __device__ __forceinline__ uint32_t wave_intra_x(const uint8_t* __restrict__ cur
 }
 
 // ---------------------------------------------------------------------------
-// Window search of one block (all threads of the group).  kTable: write the
-// block's u32 table `tab`; else write its BlockRec `rec` (SAD minimum, the
-// number of candidates that can still win and the first kShort of them) and,
-// when more than kShort can win, its overflow region `row`: the list of all
-// of them while it fits (ovf_list_cap entries), else the whole row of SADs.
+// Window search of one block (all threads of the group).  What it writes
+// depends on the kind K:
+//  kKindTable  the block's u32 table `tab`;
+//  kKindFsbm   its BlockRec `rec` (SAD minimum, the number of candidates that
+//              can still win and the first kShort of them) and, when more
+//              than kShort can win, its overflow region `row`: the list of
+//              all of them while it fits (ovf_list_cap entries), else the
+//              whole row of SADs;
+//  kKindStats  its statistics `bst`: SAD minimum, valid count,
+//              SAD_deviation and IntraX (Section 3.1).
 // `win` is the window in LDS, `red` one slot per wave, `n_keep` a shared
 // counter.
 // ---------------------------------------------------------------------------
-template <int N, int M, int R, bool kTable>
+enum : int { kKindFsbm = 0, kKindTable = 1, kKindStats = 2 };
+
+template <int N, int M, int R, int K>
 __device__ __forceinline__ void search_block(const KGeom& g, const WindowShape& s,
                                              const uint8_t* __restrict__ ref,
                                              const uint8_t* __restrict__ cur, int b,
                                              uint32_t* __restrict__ tab, BlockRec* __restrict__ rec,
                                              uint16_t* __restrict__ row, uint32_t slack,
-                                             uint32_t* win, uint64_t* red, uint32_t* n_keep) {
+                                             uint32_t* win, uint64_t* red, uint32_t* n_keep,
+                                             acbm_block_stats* __restrict__ bst = nullptr) {
+  constexpr bool kTable = K == kKindTable;
   const int r = b / g.bx, c = b - r * g.bx;
   const int x0 = c * N, y0 = r * M;
   const int p = s.p, W = 2 * p + 1;
@@ -111,6 +120,45 @@ __device__ __forceinline__ void search_block(const KGeom& g, const WindowShape& 
   // row groups beyond +-p) read as 0xFFFF from here on
   const ValidBox vbox = valid_box(p, x0, y0, N, M, g.width, g.height);
   if (active) mask_invalid<R>(acc, vbox, u0, v0);
+
+  if (K == kKindStats) {
+    // SAD_deviation = sum over the valid window of SAD - SAD_min.  Per lane
+    // at most 4*R*65280 < 2^32; per wave at most 64 times that < 2^32 for
+    // R <= 16, so u32 sums are exact and the group total is summed in u64.
+    const uint32_t lmin = active ? min_u16_lanes<R>(acc) : 0xFFFFu;
+    const uint32_t smin = (uint32_t)group_min_u64(lmin, red);
+    uint32_t dev = 0, nvalid = 0;
+    if (active) {
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t sad = (uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu;
+          if (sad != 0xFFFFu) {
+            dev += sad - smin;
+            ++nvalid;
+          }
+        }
+    }
+    dev = wave_sum_u32(dev);
+    nvalid = wave_sum_u32(nvalid);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = ((uint64_t)nvalid << 40) | dev;  // both fields stay below 2^40 and 2^24
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t d = 0, n = 0;
+      for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) {
+        d += red[w] & ((1ull << 40) - 1);
+        n += red[w] >> 40;
+      }
+      bst->sad_min = smin;
+      bst->valid = (uint32_t)n;
+      bst->sad_deviation = d;
+      bst->intra_x = intra;
+      bst->reserved = 0;
+    }
+    return;
+  }
 
   if (kTable) {
     if (!active) return;
@@ -193,11 +241,26 @@ k_search(const KGeom g, const WindowShape s, const FramePtrs fr, uint32_t* __res
   const int pair = blockIdx.y;
   const size_t WW = (size_t)(2 * s.p + 1) * (2 * s.p + 1);
   const size_t at = (size_t)pair * g.nb + b;
-  search_block<N, M, R, kTable>(g, s, fr.f[pair], fr.f[pair + 1], b,
+  search_block<N, M, R, kTable ? kKindTable : kKindFsbm>(g, s, fr.f[pair], fr.f[pair + 1], b,
                                 kTable ? table + (size_t)b * WW : nullptr,
                                 kTable ? nullptr : recs + at,
                                 kTable ? nullptr : ovf + at * ovf_stride(s.p),
                                 slack, win, red, &n_keep);
+}
+
+// Block statistics of one frame pair (Section 3.1): one workgroup per block,
+// the same window search as k_search.
+template <int N, int M, int R>
+__global__ void __launch_bounds__(1024)
+k_stats(const KGeom g, const WindowShape s, const uint8_t* __restrict__ ref,
+        const uint8_t* __restrict__ cur, acbm_block_stats* __restrict__ out) {
+  extern __shared__ uint32_t win[];
+  __shared__ uint64_t red[16];
+  __shared__ uint32_t n_keep;
+  const int b = xcd_band(blockIdx.x, g.nb);
+  if (b >= g.nb) return;
+  search_block<N, M, R, kKindStats>(g, s, ref, cur, b, nullptr, nullptr, nullptr, 0, win, red,
+                                    &n_keep, out + b);
 }
 
 // Full search over the jobs of one batch group: one workgroup per
@@ -222,7 +285,7 @@ k_search_batch(const BatchJob* __restrict__ jobs, int njobs, uint32_t items) {
   const uint32_t local = it - J.item0;
   const int pair = (int)(local / (uint32_t)g.nb), b = (int)(local % (uint32_t)g.nb);
   const size_t at = (size_t)pair * g.nb + b;
-  search_block<N, M, R, false>(g, J.s, J.frames[pair], J.frames[pair + 1], b, nullptr,
+  search_block<N, M, R, kKindFsbm>(g, J.s, J.frames[pair], J.frames[pair + 1], b, nullptr,
                                J.recs + at, J.ovf + at * ovf_stride(g.p), J.slack, win, red,
                                &n_keep);
 }
@@ -579,6 +642,42 @@ int launch_sad_table(const KGeom& g, const uint8_t* cur, const uint8_t* ref, uin
   fr.f[0] = ref;
   fr.f[1] = cur;
   return launch_search<true>(g, fr, 1, table, nullptr, nullptr, 0, st);
+}
+
+template <int N, int M>
+static int launch_stats_nm(const KGeom& g, const uint8_t* cur, const uint8_t* ref,
+                           acbm_block_stats* out, hipStream_t st) {
+  const SearchPlan pl = plan_search(g.bw, g.bh, g.p);
+  if (!pl.R) return fail(ACBM_E_UNSUPPORTED, "search window does not fit in LDS");
+  const WindowShape s = window_shape<N, M>(g.p, pl.R);
+  const int grid_x = ((g.nb + 7) / 8) * 8;
+  switch (pl.R) {
+#define ACBM_CASE(RR)                                                                       \
+  case RR: {                                                                                \
+    if (pl.lds_bytes > 64 * 1024)                                                           \
+      (void)hipFuncSetAttribute((const void*)k_stats<N, M, RR>,                             \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, pl.lds_bytes);  \
+    ProfScope ps("stats", st);                                                              \
+    hipLaunchKernelGGL((k_stats<N, M, RR>), dim3(grid_x), dim3(pl.threads), pl.lds_bytes, st, \
+                       g, s, ref, cur, out);                                                \
+    break;                                                                                  \
+  }
+    ACBM_R_LIST(ACBM_CASE)
+#undef ACBM_CASE
+    default:
+      return fail(ACBM_E_UNSUPPORTED, "no search kernel for this row blocking");
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ACBM_OK : hip_fail(e, "launching the block statistics");
+}
+
+int launch_sad_stats(const KGeom& g, const uint8_t* cur, const uint8_t* ref,
+                     acbm_block_stats* out, hipStream_t st) {
+  if (g.bw == 16 && g.bh == 16) return launch_stats_nm<16, 16>(g, cur, ref, out, st);
+  if (g.bw == 16 && g.bh == 8) return launch_stats_nm<16, 8>(g, cur, ref, out, st);
+  if (g.bw == 8 && g.bh == 16) return launch_stats_nm<8, 16>(g, cur, ref, out, st);
+  if (g.bw == 8 && g.bh == 8) return launch_stats_nm<8, 8>(g, cur, ref, out, st);
+  return fail(ACBM_E_UNSUPPORTED, "block size must be 8 or 16 in each direction");
 }
 
 static size_t ovf_row_bytes(const KGeom& g) { return ovf_stride(g.p) * sizeof(uint16_t); }

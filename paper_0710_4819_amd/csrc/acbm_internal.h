@@ -121,6 +121,8 @@ class ProfScope {
 };
 
 // Launchers.  All enqueue on `s` and return ACBM_* codes.
+int launch_sad_stats(const KGeom& g, const uint8_t* cur, const uint8_t* ref,
+                     acbm_block_stats* out, hipStream_t st);
 int launch_sad_table(const KGeom& g, const uint8_t* cur, const uint8_t* ref, uint32_t* table,
                      hipStream_t s);
 size_t fsbm_ws_bytes(const KGeom& g, uint32_t npairs);

@@ -113,6 +113,49 @@ def planted_blocks(h=144, w=176, block=16, p=7, noise_sigma=2.0, blur_sigma=1.5,
 
 
 # --------------------------------------------------------------------------
+# Fig. 3 setup: one original frame, nine known global vectors
+# --------------------------------------------------------------------------
+def global_motion(h=288, w=352, block=16, p=16, nframes=10, max_shift=8, noise_sigma=2.0,
+                  seed=6000) -> Workload:
+    """Section 3.1's experimental setup (Fig. 3): a ten-frame sequence made
+    from one original picture by nine known global vectors.
+
+    The original is a canvas larger than the frame whose local texture
+    strength varies smoothly: a fine texture (sigma 1.2) and a very smooth one
+    (sigma 8) are mixed with a weight field that is itself blurred noise
+    (sigma 24), so blocks range from flat to highly textured.  Frame k is the
+    canvas cropped at the cumulative offset o_k, so frame k shows at x what
+    frame k-1 showed at x + (o_k - o_{k-1}): every block of pair k has the
+    true vector d_k = o_k - o_{k-1}, drawn uniformly from
+    [-max_shift, max_shift]^2.  Each frame then gets N(0, noise_sigma^2)."""
+    g = rng(seed)
+    d = g.integers(-max_shift, max_shift + 1, size=(nframes - 1, 2), dtype=np.int64)
+    off = np.vstack([np.zeros((1, 2), np.int64), np.cumsum(d, axis=0)])
+    lo = off.min(axis=0)
+    span = off.max(axis=0) - lo
+    ch, cw = h + int(span[1]), w + int(span[0])
+    fine = texture(ch, cw, 1.2, rng(seed + 1)).astype(np.int64)
+    smooth = texture(ch, cw, 8.0, rng(seed + 2)).astype(np.int64)
+    wgt = blur(rng(seed + 3).integers(0, 256, size=(ch, cw), dtype=np.int64).astype(np.uint8),
+               24.0).astype(np.int64)
+    # stretch the weight field to the full 0..256 range (integer arithmetic)
+    wmin, wmax = int(wgt.min()), int(wgt.max())
+    wq = (wgt - wmin) * 256 // max(1, wmax - wmin)
+    canvas = ((wq * fine + (256 - wq) * smooth + 128) >> 8).astype(np.uint8)
+    frames = []
+    for k in range(nframes):
+        ox, oy = int(off[k, 0] - lo[0]), int(off[k, 1] - lo[1])
+        f = canvas[oy:oy + h, ox:ox + w]
+        frames.append(add_noise(f, noise_sigma, rng(seed + 100 + k)))
+    by, bx = h // block, w // block
+    truth = np.empty((nframes - 1, by, bx, 2), np.int16)
+    truth[..., 0] = d[:, 0, None, None]
+    truth[..., 1] = d[:, 1, None, None]
+    return Workload("global_motion_fig3", frames, block, block, p, 0, 0, truth,
+                    {"shifts": d.tolist(), "noise_sigma": noise_sigma})
+
+
+# --------------------------------------------------------------------------
 # Panned background plus bouncing textured rectangles
 # --------------------------------------------------------------------------
 def moving_scene(h: int, w: int, nframes: int, n_obj: int, size_range, vel_max: int,

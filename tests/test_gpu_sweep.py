@@ -1,0 +1,74 @@
+"""GPU checks of the threshold and frame-rate sweep (one batched launch of
+FSBM, PBM and ACBM jobs over shared frames) against the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_0710_4819_amd import acbm, synth, sweep
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("mv_x", "mv_y", "sad", "j", "rate_bits", "cands", "mode", "intra_x")
+ALGO = {"FSBM": oracle.FSBM, "PBM": oracle.PBM, "ACBM": oracle.ACBM}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _oracle_row(frames, row, settings_by_label, p=16):
+    s = settings_by_label.get(row["setting"]) or sweep.PAPER
+    prm = oracle.Params(lam=row["lam"], qp=row["lam"], alpha=s.alpha, beta=s.beta,
+                        gamma_num=s.gamma_num, gamma_den=s.gamma_den)
+    res = oracle.sequence(frames[::row["step"]], 16, 16, p, prm, ALGO[row["algo"]])
+    return sweep.aggregate(res), res
+
+
+def test_small_sweep_every_job_equals_oracle():
+    """Six CIF frames, lambda 2 and 32, 30 and 10 fps, three settings that
+    span the extremes (every block critical; no block critical; the paper's):
+    each job's aggregate equals the oracle's run of the same sequence."""
+    wl = synth.cif_scene(nframes=7)
+    settings = [sweep.Setting(0, 0, 0, 1), sweep.Setting(1 << 20, 0, 0, 1), sweep.PAPER]
+    say("[sweep] small: cif 7 frames, lambdas (2, 32), steps (1, 3), 3 settings")
+    rows = sweep.run(wl.frames, 16, 16, 16, lams=(2, 32), steps=(1, 3), settings=settings)
+    assert len(rows) == 2 * 2 * (2 + 3)
+    by_label = {s.label: s for s in settings}
+    for row in rows:
+        want, _ = _oracle_row(wl.frames, row, by_label)
+        got = {k: row[k] for k in want}
+        assert got == want, (row["algo"], row["lam"], row["step"], row["setting"])
+    crit = {r["setting"]: r["critical_frac"] for r in rows if r["algo"] == "ACBM"}
+    assert crit[settings[0].label] == 1.0 and crit[settings[1].label] == 0.0
+
+
+def test_full_grid_trends_and_paper_rows_equal_oracle():
+    """The CIF sequence (30 frames, p = 16) over the default grid at lambda
+    2, 8, 32 and 30/10 fps, in one batch.  The FSBM, PBM and paper-setting
+    ACBM rows equal the oracle.  A critical block counts its PBM positions
+    (at most 14 predictors + 8 ring positions) and the whole window, so no
+    setting exceeds FSBM by more than 22 positions per block.  And the
+    Table 1 trends hold on these synthetic frames: with the paper's setting
+    ACBM searches fewer positions than FSBM, more at 10 fps than at 30 fps,
+    and fewer at lambda 32 than at lambda 2."""
+    wl = synth.cif_scene(nframes=30)
+    say("[sweep] full grid: cif 30 frames, 45 settings x 3 lambdas x 2 steps")
+    rows = sweep.run(wl.frames, 16, 16, 16)
+    assert len(rows) == 3 * 2 * (2 + len(sweep.grid()))
+    fsbm = {(r["lam"], r["step"]): r["cands_per_block"] for r in rows if r["algo"] == "FSBM"}
+    for row in rows:
+        if row["algo"] == "ACBM":
+            assert row["cands_per_block"] <= fsbm[(row["lam"], row["step"])] + 22, row
+    paper = {(r["lam"], r["step"], r["algo"]): r for r in rows
+             if r["algo"] != "ACBM" or r["setting"] == sweep.PAPER.label}
+    for (lam, step), f in fsbm.items():
+        assert paper[(lam, step, "ACBM")]["cands_per_block"] < f
+    for key, row in sorted(paper.items()):
+        want, _ = _oracle_row(wl.frames, row, {})
+        assert {k: row[k] for k in want} == want, key
+    for lam in (2, 8):
+        assert paper[(lam, 3, "ACBM")]["cands_per_block"] > paper[(lam, 1, "ACBM")]["cands_per_block"]
+    for step in (1, 3):
+        assert paper[(32, step, "ACBM")]["critical_frac"] < paper[(2, step, "ACBM")]["critical_frac"]
+    say(sweep.table(rows))
