@@ -34,7 +34,8 @@ class _Geom(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("lambda_", C.c_uint32), ("qp", C.c_uint32), ("alpha", C.c_uint32),
-                ("beta", C.c_uint32), ("gamma_num", C.c_uint32), ("gamma_den", C.c_uint32)]
+                ("beta", C.c_uint32), ("gamma_num", C.c_uint32), ("gamma_den", C.c_uint32),
+                ("subpel", C.c_uint32)]
 
 
 @dataclass(frozen=True)
@@ -42,7 +43,8 @@ class Params:
     """Lagrange multiplier, quantiser and the ACBM thresholds.
 
     The paper's tuned values for 16x16 macroblocks are alpha = 1000,
-    beta = 8, gamma = 1/4 (Section 4).
+    beta = 8, gamma = 1/4 (Section 4).  subpel = 1: half-pel precision, all
+    vectors in half-pel units.
     """
     lam: int = 0
     qp: int = 0
@@ -50,9 +52,11 @@ class Params:
     beta: int = 8
     gamma_num: int = 1
     gamma_den: int = 4
+    subpel: int = 0
 
     def _c(self) -> _Params:
-        return _Params(self.lam, self.qp, self.alpha, self.beta, self.gamma_num, self.gamma_den)
+        return _Params(self.lam, self.qp, self.alpha, self.beta, self.gamma_num, self.gamma_den,
+                       self.subpel)
 
 
 _lib = None
@@ -83,6 +87,10 @@ def _bind(lib):
                                  P(C.c_int32), C.c_int, C.c_int, C.c_void_p]
     lib.oracle_sad_deviation.argtypes = [P(_Geom), u8p, u8p, C.c_int, C.c_int,
                                          P(C.c_uint64), P(C.c_uint32)]
+    lib.oracle_ref_half.argtypes = [P(_Geom), u8p, C.c_long, C.c_long]
+    lib.oracle_is_valid_half.argtypes = [P(_Geom), C.c_int, C.c_int, C.c_int, C.c_int]
+    lib.oracle_sad_half.argtypes = [P(_Geom), u8p, u8p, C.c_int, C.c_int, C.c_int, C.c_int]
+    lib.oracle_sad_half.restype = C.c_uint32
     return lib
 
 
@@ -155,6 +163,20 @@ def is_valid(g: _Geom, r: int, c: int, u: int, v: int) -> bool:
 def sad(cur, ref, g: _Geom, r, c, u, v) -> int:
     cur, ref = _frame(cur), _frame(ref)
     return int(_load().oracle_sad(C.byref(g), _u8p(cur), _u8p(ref), r, c, u, v))
+
+
+def ref_half(ref, g: _Geom, X: int, Y: int) -> int:
+    ref = _frame(ref)
+    return int(_load().oracle_ref_half(C.byref(g), _u8p(ref), X, Y))
+
+
+def is_valid_half(g: _Geom, r: int, c: int, U: int, V: int) -> bool:
+    return bool(_load().oracle_is_valid_half(C.byref(g), r, c, U, V))
+
+
+def sad_half(cur, ref, g: _Geom, r, c, U, V) -> int:
+    cur, ref = _frame(cur), _frame(ref)
+    return int(_load().oracle_sad_half(C.byref(g), _u8p(cur), _u8p(ref), r, c, U, V))
 
 
 def intra_x(cur, g: _Geom, r, c) -> int:

@@ -103,6 +103,66 @@ uint32_t oracle_sad(const oracle_geom* g, const uint8_t* cur, const uint8_t* ref
 }
 
 /* ------------------------------------------------------------------------ */
+/* Half-pel precision (Section 2.2: the PBM refinement normally works on the */
+/* half-pixel grid; Table 1's 969 full-search positions at p = 15 are the    */
+/* 961 integer ones plus 8 half-pel ones).  The paper's simulations use an   */
+/* H.263 coder (Section 4), so the half-pel reference is H.263's bilinear    */
+/* interpolation: at half-pel coordinates (X, Y) = (2x + fx, 2y + fy)        */
+/*   fx = fy = 0: A                                                          */
+/*   fx = 1, fy = 0: (A + B + 1) / 2        fx = 0, fy = 1: (A + C + 1) / 2  */
+/*   fx = fy = 1: (A + B + C + D + 2) / 4                                    */
+/* with A = ref(x, y), B = ref(x+1, y), C = ref(x, y+1), D = ref(x+1, y+1)   */
+/* and integer division (all terms are >= 0).                                */
+/* ------------------------------------------------------------------------ */
+static long half_floor(long X) { return X >= 0 ? X / 2 : -((-X + 1) / 2); }
+
+int oracle_ref_half(const oracle_geom* g, const uint8_t* ref, long X, long Y)
+{
+    long x = half_floor(X), y = half_floor(Y);
+    int fx = (int)(X - 2 * x), fy = (int)(Y - 2 * y);
+    int A = ref[y * g->pitch + x];
+    if (!fx && !fy) return A;
+    if (fx && !fy) return (A + ref[y * g->pitch + x + 1] + 1) / 2;
+    if (!fx && fy) return (A + ref[(y + 1) * g->pitch + x] + 1) / 2;
+    return (A + ref[y * g->pitch + x + 1] + ref[(y + 1) * g->pitch + x] +
+            ref[(y + 1) * g->pitch + x + 1] + 2) / 4;
+}
+
+/* A half-pel candidate (U, V) (units of half a pixel) is valid when each    */
+/* component is within the window (|U|, |V| <= 2p) and every reference pixel */
+/* the interpolation reads lies inside the frame.  Pixel (i, j) of the block */
+/* reads columns floor((2(x0+i) + U)/2) and, when U is odd, the next one;    */
+/* the extremes are i = 0 and i = N-1 (rows likewise).                       */
+int oracle_is_valid_half(const oracle_geom* g, int r, int c, int U, int V)
+{
+    long p2 = 2 * (long)g->p;
+    long x0 = (long)c * g->block_w, y0 = (long)r * g->block_h;
+    if (U < -p2 || U > p2 || V < -p2 || V > p2) return 0;
+    long xlo = half_floor(2 * x0 + U);
+    long xhi = half_floor(2 * (x0 + (long)g->block_w - 1) + U) + (U & 1 ? 1 : 0);
+    long ylo = half_floor(2 * y0 + V);
+    long yhi = half_floor(2 * (y0 + (long)g->block_h - 1) + V) + (V & 1 ? 1 : 0);
+    return xlo >= 0 && xhi <= (long)g->width - 1 && ylo >= 0 && yhi <= (long)g->height - 1;
+}
+
+/* SAD of a half-pel candidate: the SAD equation of Section 2.1 with the     */
+/* candidate pixel taken from the half-pel reference.                        */
+uint32_t oracle_sad_half(const oracle_geom* g, const uint8_t* cur, const uint8_t* ref,
+                         int r, int c, int U, int V)
+{
+    long x0 = (long)c * g->block_w, y0 = (long)r * g->block_h;
+    uint32_t s = 0;
+    for (long j = 0; j < (long)g->block_h; j++) {
+        for (long i = 0; i < (long)g->block_w; i++) {
+            int a = cur[(y0 + j) * g->pitch + (x0 + i)];
+            int b = oracle_ref_half(g, ref, 2 * (x0 + i) + U, 2 * (y0 + j) + V);
+            s += (uint32_t)abs(a - b);
+        }
+    }
+    return s;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Intra_SAD (Section 3.1): sum of |p_t(i,j) - mu| with mu the block mean.   */
 /* mu = S/(NM) is rational; multiplying every term by NM keeps it exact:     */
 /* IntraX = NM * Intra_SAD = sum |NM * p_t(i,j) - S|.                        */
@@ -188,19 +248,31 @@ typedef struct cand_eval {
     uint32_t raster;
 } cand_eval;
 
+/* Vectors are in units of 1/s pixel: s = 1 (integer) or s = 2 (half-pel).  */
+/* The rate, the |u|+|v| tie-break and the raster position are all taken in  */
+/* those units (the half-pel window is (4p+1) x (4p+1)).                     */
+static int units(const oracle_params* prm) { return prm->subpel ? 2 : 1; }
+
+static int valid_in_units(const oracle_geom* g, const oracle_params* prm, int r, int c,
+                          int u, int v)
+{
+    return prm->subpel ? oracle_is_valid_half(g, r, c, u, v) : oracle_is_valid(g, r, c, u, v);
+}
+
 static cand_eval evaluate(const oracle_geom* g, const oracle_params* prm,
                           const uint8_t* cur, const uint8_t* ref, int r, int c,
                           int u, int v, int px, int py)
 {
     cand_eval e;
-    int p = (int)g->p;
+    int sp = units(prm) * (int)g->p;
     e.u = u;
     e.v = v;
-    e.sad = oracle_sad(g, cur, ref, r, c, u, v);
+    e.sad = prm->subpel ? oracle_sad_half(g, cur, ref, r, c, u, v)
+                        : oracle_sad(g, cur, ref, r, c, u, v);
     e.rate = (uint32_t)(oracle_se_bits((int64_t)u - px) + oracle_se_bits((int64_t)v - py));
     e.j = (uint64_t)e.sad + (uint64_t)prm->lambda * e.rate;
     e.l1 = (uint32_t)(abs(u) + abs(v));
-    e.raster = (uint32_t)((v + p) * (2 * p + 1) + (u + p));
+    e.raster = (uint32_t)((v + sp) * (2 * sp + 1) + (u + sp));
     return e;
 }
 
@@ -225,20 +297,34 @@ static void store(oracle_result* o, const cand_eval* e, uint32_t cands, uint32_t
 }
 
 /* Full search over the window of one block (Section 2.3): every valid       */
-/* position is evaluated and the cheapest kept.  Returns the number of       */
-/* positions evaluated.                                                      */
+/* integer position is evaluated and the cheapest kept.  With half-pel       */
+/* precision the 8 half-pel positions around that winner are evaluated next  */
+/* (Table 1 counts them: 969 = 31^2 + 8 at p = 15) and the cheapest of all   */
+/* is the result.  Returns the number of positions evaluated.                */
 static uint32_t full_search(const oracle_geom* g, const oracle_params* prm,
                             const uint8_t* cur, const uint8_t* ref, int r, int c,
                             int px, int py, cand_eval* best)
 {
-    int p = (int)g->p;
+    int p = (int)g->p, s = units(prm);
     uint32_t count = 0;
     for (int v = -p; v <= p; v++) {
         for (int u = -p; u <= p; u++) {
             if (!oracle_is_valid(g, r, c, u, v)) continue;
-            cand_eval e = evaluate(g, prm, cur, ref, r, c, u, v, px, py);
+            cand_eval e = evaluate(g, prm, cur, ref, r, c, s * u, s * v, px, py);
             if (count == 0 || cheaper(&e, best)) *best = e;
             count++;
+        }
+    }
+    if (prm->subpel) {
+        int cu = best->u, cv = best->v; /* the integer winner, on the even grid */
+        for (int dv = -1; dv <= 1; dv++) {
+            for (int du = -1; du <= 1; du++) {
+                if (du == 0 && dv == 0) continue;
+                if (!oracle_is_valid_half(g, r, c, cu + du, cv + dv)) continue;
+                cand_eval e = evaluate(g, prm, cur, ref, r, c, cu + du, cv + dv, px, py);
+                if (cheaper(&e, best)) *best = e;
+                count++;
+            }
         }
     }
     return count;
@@ -287,6 +373,7 @@ static int check_params(const oracle_params* prm)
 {
     if (!prm) return ORACLE_EINVAL;
     if (prm->gamma_den == 0) return ORACLE_EINVAL;
+    if (prm->subpel > 1) return ORACLE_EINVAL;
     return ORACLE_OK;
 }
 
@@ -329,8 +416,10 @@ int oracle_fsbm_frame(const oracle_geom* g, const oracle_params* prm,
 /*     outside the block grid are absent; predictors that are not valid      */
 /*     candidates for this block are dropped; repeats count once.            */
 /*  2. the cheapest predictor;                                               */
-/*  3. one refinement step: the valid integer 8-neighbours of that           */
-/*     predictor not already evaluated, then the cheapest of everything.     */
+/*  3. one refinement step: the valid 8-neighbours of that predictor on the */
+/*     finest grid in use (integer, or half-pel with subpel: "normally" the  */
+/*     half-pixel grid, Section 2.2) not already evaluated, then the         */
+/*     cheapest of everything.  Vectors of the fields are in the same units. */
 /* ------------------------------------------------------------------------ */
 #define MAX_SET 32
 
@@ -373,7 +462,7 @@ static void pbm_block(const oracle_geom* g, const oracle_params* prm,
     cand_eval set[MAX_SET];
     int n = 0;
     for (int k = 0; k < np; k++) {
-        if (!oracle_is_valid(g, r, c, pu[k], pv[k])) continue;
+        if (!valid_in_units(g, prm, r, c, pu[k], pv[k])) continue;
         if (in_set(set, n, pu[k], pv[k])) continue;
         set[n++] = evaluate(g, prm, cur, ref, r, c, pu[k], pv[k], px, py);
     }
@@ -383,12 +472,12 @@ static void pbm_block(const oracle_geom* g, const oracle_params* prm,
     for (int k = 1; k < n; k++)
         if (cheaper(&set[k], &b0)) b0 = set[k];
 
-    /* step 3: refinement around it on the integer grid */
+    /* step 3: refinement around it, one step of the finest grid */
     for (int dv = -1; dv <= 1; dv++) {
         for (int du = -1; du <= 1; du++) {
             if (du == 0 && dv == 0) continue;
             int u = b0.u + du, v = b0.v + dv;
-            if (!oracle_is_valid(g, r, c, u, v)) continue;
+            if (!valid_in_units(g, prm, r, c, u, v)) continue;
             if (in_set(set, n, u, v)) continue;
             set[n++] = evaluate(g, prm, cur, ref, r, c, u, v, px, py);
         }

@@ -35,11 +35,15 @@ typedef struct oracle_geom {
 } oracle_geom;
 
 /* Lagrange multiplier and the ACBM thresholds (Sections 2.1 and 3.2).
- * gamma = gamma_num / gamma_den. */
+ * gamma = gamma_num / gamma_den.  subpel = 1 selects half-pel precision
+ * (Section 2.2's refinement on the half-pixel grid, and the 8 half-pel
+ * positions of the full search counted in Table 1): every vector, predictor
+ * and rate is then in half-pel units. */
 typedef struct oracle_params {
     uint32_t lambda, qp;
     uint32_t alpha, beta;
     uint32_t gamma_num, gamma_den;
+    uint32_t subpel;
 } oracle_params;
 
 /* One block's outcome.  Deliberately a different layout from the GPU
@@ -72,6 +76,13 @@ int      oracle_is_valid(const oracle_geom* g, int r, int c, int u, int v);
 uint32_t oracle_sad(const oracle_geom* g, const uint8_t* cur, const uint8_t* ref,
                     int r, int c, int u, int v);
 uint64_t oracle_intra_x(const oracle_geom* g, const uint8_t* cur, int r, int c);
+/* Half-pel sample of the reference at half-pel coordinates (X, Y) = (2x + fx,
+ * 2y + fy) (bilinear, rounding as H.263), and the SAD and validity of a
+ * half-pel candidate (U, V) of block (r, c). */
+int      oracle_ref_half(const oracle_geom* g, const uint8_t* ref, long X, long Y);
+int      oracle_is_valid_half(const oracle_geom* g, int r, int c, int U, int V);
+uint32_t oracle_sad_half(const oracle_geom* g, const uint8_t* cur, const uint8_t* ref,
+                         int r, int c, int U, int V);
 void     oracle_median_pred(const int32_t* field_x, const int32_t* field_y,
                             int bx, int r, int c, int* px, int* py);
 

@@ -523,11 +523,6 @@ def run_all(lib_path: str | None = None) -> list:
     return failed
 
 
-if __name__ == "__main__":
-    import sys
-    bad = run_all(sys.argv[1] if len(sys.argv) > 1 else None)
-    print(" ".join(bad) if bad else "all pins hold")
-    sys.exit(1 if bad else 0)
 
 
 def pin_block_matches_raster():
@@ -549,3 +544,157 @@ def pin_block_matches_raster():
 
 
 ALL_PINS.append(pin_block_matches_raster)
+
+
+# ----------------------------------------------------------------------------
+# half-pel precision
+# ----------------------------------------------------------------------------
+def _half_frame_from(ref, U, V):
+    """The frame whose every pixel is ref's half-pel sample at (2x + U, 2y + V)
+    (brute force's sampler), ref's own pixel where that sample would leave
+    the frame."""
+    h, w = ref.shape
+    rows = brute.as_lists(ref)
+    out = ref.copy()
+    for y in range(h):
+        for x in range(w):
+            X, Y = 2 * x + U, 2 * y + V
+            if 0 <= X // 2 and X // 2 + (X & 1) < w and 0 <= Y // 2 and Y // 2 + (Y & 1) < h:
+                out[y, x] = brute.half_sample(rows, X, Y)
+    return out
+
+
+def pin_half_sample_values():
+    """Hand-worked H.263 half-pel samples (rounding half up), and the brute
+    force's sampler on the same values."""
+    with open(golden("half_pel_samples.txt")) as f:
+        rows = [l.split("#")[0].split() for l in f if l.strip() and not l.startswith("#")]
+    for kind, A, B, C, D, want in rows:
+        A, B, C, D, want = int(A), int(B), int(C), int(D), int(want)
+        ref = np.array([[A, B, 0], [C, D, 0], [0, 0, 0]], np.uint8)
+        g = oracle.geom(ref, 1, 1, 0)
+        X, Y = {"h": (1, 0), "v": (0, 1), "d": (1, 1)}[kind]
+        assert oracle.ref_half(ref, g, X, Y) == want, (kind, A, B, C, D)
+        assert brute.half_sample(brute.as_lists(ref), X, Y) == want
+
+
+def pin_half_sample_brute():
+    """Every half-pel sample of a small frame equals the brute force's, and
+    even coordinates are the integer pixels themselves."""
+    ref = _noise(7, 9, 611)
+    g = oracle.geom(ref, 1, 1, 0)
+    rows = brute.as_lists(ref)
+    for Y in range(0, 2 * 7 - 1):
+        for X in range(0, 2 * 9 - 1):
+            assert oracle.ref_half(ref, g, X, Y) == brute.half_sample(rows, X, Y), (X, Y)
+            if X % 2 == 0 and Y % 2 == 0:
+                assert oracle.ref_half(ref, g, X, Y) == int(ref[Y // 2, X // 2])
+
+
+def pin_half_valid_and_sad():
+    """Half-pel validity and SAD against brute force over whole windows
+    (negative and odd displacements at every border included); on the even
+    grid they reduce to the integer validity and SAD."""
+    for (h, w, bw, bh, p, seed) in [(12, 16, 4, 4, 2, 621), (16, 12, 8, 4, 3, 622)]:
+        cur, ref = _noise(h, w, seed), _noise(h, w, seed + 1)
+        g = oracle.geom(cur, bw, bh, p)
+        cl, rl = brute.as_lists(cur), brute.as_lists(ref)
+        for r in range(h // bh):
+            for c in range(w // bw):
+                x0, y0 = c * bw, r * bh
+                for V in range(-2 * p - 1, 2 * p + 2):
+                    for U in range(-2 * p - 1, 2 * p + 2):
+                        ok = brute.half_valid(w, h, bw, bh, p, x0, y0, U, V)
+                        assert oracle.is_valid_half(g, r, c, U, V) == ok, (r, c, U, V)
+                        if U % 2 == 0 and V % 2 == 0:
+                            assert ok == oracle.is_valid(g, r, c, U // 2, V // 2)
+                        if ok:
+                            s = oracle.sad_half(cur, ref, g, r, c, U, V)
+                            assert s == brute.half_sad(cl, rl, x0, y0, bw, bh, U, V), (r, c, U, V)
+                            if U % 2 == 0 and V % 2 == 0:
+                                assert s == oracle.sad(cur, ref, g, r, c, U // 2, V // 2)
+
+
+def _half_cases():
+    return [cs for i, cs in enumerate(_tiny_cases()) if i % 3 == 0]
+
+
+def pin_brute_half():
+    """FSBM, PBM and ACBM with half-pel precision against the brute force on
+    tiny frames of every kind (with temporal fields in half-pel units)."""
+    for i, (cur, ref, bw, bh, p) in enumerate(_half_cases()):
+        lam = [0, 1, 4, 32][i % 4]
+        cl, rl = brute.as_lists(cur), brute.as_lists(ref)
+        got = oracle.fsbm_frame(cur, ref, bw, bh, p, oracle.Params(lam=lam, subpel=1))
+        _same(got, brute.fsbm(cl, rl, bw, bh, p, lam, half=True), f"half fsbm case {i}")
+        prev = None
+        if i % 2:
+            prev = _prev_for(cur, bw, bh, 2 * p, 970 + i)
+        pv = None if prev is None else {(r, c): (int(prev[r, c, 0]), int(prev[r, c, 1]))
+                                        for r in range(prev.shape[0]) for c in range(prev.shape[1])}
+        got = oracle.pbm_frame(cur, ref, bw, bh, p, oracle.Params(lam=lam, subpel=1),
+                               prev_field=prev)
+        _same(got, brute.predictive(cl, rl, bw, bh, p, lam, prev=pv, half=True),
+              f"half pbm case {i}")
+        nm = bw * bh
+        prm = oracle.Params(lam=lam, qp=lam, alpha=[0, 3, 40, 1000][i % 4] * nm // 16,
+                            beta=[0, 1, 2, 8][(i // 4) % 4], gamma_num=1,
+                            gamma_den=[1, 4, 2, 4][(i // 2) % 4], subpel=1)
+        got = oracle.acbm_frame(cur, ref, bw, bh, p, prm, prev_field=prev)
+        want = brute.predictive(cl, rl, bw, bh, p, lam, prev=pv, half=True,
+                                acbm=(prm.alpha, prm.beta, prm.qp, prm.gamma_num, prm.gamma_den))
+        _same(got, want, f"half acbm case {i}")
+
+
+def pin_half_table1_count():
+    """Table 1 / Section 4: full search at p = 15 evaluates 969 positions per
+    interior macroblock with half-pel precision (961 integer + 8 half-pel)."""
+    kv = read_kv("paper_counts.txt")
+    p, want = int(kv["p"]), int(kv["fsbm_positions_p15_halfpel"])
+    ref = synth.texture(96, 96, 1.5, synth.rng(631))
+    cur = synth.add_noise(np.roll(ref, (1, -1), (0, 1)), 1.0, synth.rng(632))
+    res = oracle.fsbm_frame(cur, ref, 16, 16, p, oracle.Params(lam=2, subpel=1))
+    inner = res[1:5, 1:5]  # blocks with the whole +-15 window inside the frame
+    assert (inner["cands"] == want).all(), inner["cands"]
+
+
+def pin_half_planted():
+    """Planted half-pel motion (the Section 3.1 method on the half grid):
+    the current frame is the reference sampled at a known half-pel offset by
+    the brute force's sampler, so the planted vector has SAD 0 and FSBM with
+    lambda = 0 must return it on every block where it is valid.  And on the
+    even grid the half-pel search starts from the integer one: its SAD is
+    never above the integer FSBM's, and an even result is twice that vector."""
+    ref = synth.texture(48, 64, 1.5, synth.rng(641))
+    for (U, V) in [(3, -1), (-2, 1), (1, 1), (0, -3)]:
+        cur = _half_frame_from(ref, U, V)
+        g = oracle.geom(cur, 16, 16, 3)
+        half = oracle.fsbm_frame(cur, ref, 16, 16, 3, oracle.Params(lam=0, subpel=1))
+        full = oracle.fsbm_frame(cur, ref, 16, 16, 3, oracle.Params(lam=0))
+        by, bx = half.shape
+        checked = 0
+        for r in range(by):
+            for c in range(bx):
+                assert int(half["sad"][r, c]) <= int(full["sad"][r, c])
+                hx, hy = int(half["mv_x"][r, c]), int(half["mv_y"][r, c])
+                if hx % 2 == 0 and hy % 2 == 0:
+                    assert (hx // 2, hy // 2) == (int(full["mv_x"][r, c]), int(full["mv_y"][r, c]))
+                x0, y0 = c * 16, r * 16
+                # the planted samples cover the block only away from the borders
+                if not (1 <= x0 and x0 + 17 <= 64 and 1 <= y0 and y0 + 17 <= 48):
+                    continue
+                if oracle.is_valid_half(g, r, c, U, V):
+                    assert (hx, hy, int(half["sad"][r, c])) == (U, V, 0), (U, V, r, c)
+                    checked += 1
+        assert checked >= 2, (U, V)
+
+
+ALL_PINS += [pin_half_sample_values, pin_half_sample_brute, pin_half_valid_and_sad,
+             pin_brute_half, pin_half_table1_count, pin_half_planted]
+
+
+if __name__ == "__main__":
+    import sys
+    bad = run_all(sys.argv[1] if len(sys.argv) > 1 else None)
+    print(" ".join(bad) if bad else "all pins hold")
+    sys.exit(1 if bad else 0)

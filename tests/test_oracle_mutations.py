@@ -19,11 +19,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "acbm_oracle.c")
 
 MUTATIONS = [
-    ("sad_no_abs", "s += (uint32_t)abs(a - b);", "s += (uint32_t)(a - b);"),
+    ("sad_no_abs", "int b = ref[(y0 + j + v) * g->pitch + (x0 + i + u)];\n            s += (uint32_t)abs(a - b);",
+     "int b = ref[(y0 + j + v) * g->pitch + (x0 + i + u)];\n            s += (uint32_t)(a - b);"),
     ("sad_sign_u", "ref[(y0 + j + v) * g->pitch + (x0 + i + u)]",
      "ref[(y0 + j + v) * g->pitch + (x0 + i - u)]"),
-    ("sad_swap_uv", "e.sad = oracle_sad(g, cur, ref, r, c, u, v);",
-     "e.sad = oracle_is_valid(g, r, c, v, u) ? oracle_sad(g, cur, ref, r, c, v, u) : 0;"),
+    ("sad_swap_uv", ": oracle_sad(g, cur, ref, r, c, u, v);",
+     ": (oracle_is_valid(g, r, c, v, u) ? oracle_sad(g, cur, ref, r, c, v, u) : 0);"),
     ("se_len_plus", "return 2 * n - 1;", "return 2 * n + 1;"),
     ("se_zero_map", "(k > 0) ? (uint64_t)(2 * k - 1)", "(k >= 0) ? (uint64_t)(2 * k - 1)"),
     ("rate_drops_y", "(oracle_se_bits((int64_t)u - px) + oracle_se_bits((int64_t)v - py))",
@@ -54,6 +55,29 @@ MUTATIONS = [
     ("critical_zero_pred", "uint32_t n = full_search(g, prm, cur, ref, r, c, px, py, &fs);",
      "uint32_t n = full_search(g, prm, cur, ref, r, c, 0, 0, &fs);"),
     ("critical_count", "store(o, &fs, cands + n, 3, intra);", "store(o, &fs, n, 3, intra);"),
+    # half-pel precision
+    ("half_h_no_round", "(A + ref[y * g->pitch + x + 1] + 1) / 2", "(A + ref[y * g->pitch + x + 1]) / 2"),
+    ("half_v_no_round", "(A + ref[(y + 1) * g->pitch + x] + 1) / 2",
+     "(A + ref[(y + 1) * g->pitch + x]) / 2"),
+    ("half_diag_round", "ref[(y + 1) * g->pitch + x + 1] + 2) / 4", "ref[(y + 1) * g->pitch + x + 1] + 1) / 4"),
+    ("half_diag_as_h", "if (fx && !fy) return", "if (fx) return"),
+    ("half_v_uses_right", "(A + ref[(y + 1) * g->pitch + x] + 1) / 2",
+     "(A + ref[y * g->pitch + x + 1] + 1) / 2"),
+    ("half_floor_truncates", "return X >= 0 ? X / 2 : -((-X + 1) / 2);", "return X / 2;"),
+    ("half_valid_no_extra", "+ (U & 1 ? 1 : 0);", ";"),
+    ("half_valid_no_window", "if (U < -p2 || U > p2 || V < -p2 || V > p2) return 0;", ""),
+    ("half_sad_sign", "oracle_ref_half(g, ref, 2 * (x0 + i) + U, 2 * (y0 + j) + V)",
+     "oracle_ref_half(g, ref, 2 * (x0 + i) - U, 2 * (y0 + j) + V)"),
+    ("fsbm_no_half_step", "if (prm->subpel) {\n        int cu", "if (0) {\n        int cu"),
+    ("fsbm_half_around_origin", "int cu = best->u, cv = best->v;", "int cu = 0, cv = 0;"),
+    ("fsbm_int_grid_unscaled", "evaluate(g, prm, cur, ref, r, c, s * u, s * v, px, py)",
+     "evaluate(g, prm, cur, ref, r, c, u, v, px, py)"),
+    ("pbm_ring_integer_step", "int u = b0.u + du, v = b0.v + dv;",
+     "int u = b0.u + units(prm) * du, v = b0.v + units(prm) * dv;"),
+    ("pbm_integer_validity", "if (!valid_in_units(g, prm, r, c, pu[k], pv[k])) continue;",
+     "if (!oracle_is_valid(g, r, c, pu[k], pv[k])) continue;"),
+    ("half_rate_integer_units", "e.rate = (uint32_t)(oracle_se_bits((int64_t)u - px) + oracle_se_bits((int64_t)v - py));",
+     "e.rate = (uint32_t)(oracle_se_bits(((int64_t)u - px) / units(prm)) + oracle_se_bits(((int64_t)v - py) / units(prm)));"),
     ("seq_field_transposed", "prev[2 * b + 0] = (int16_t)o[b].mv_x;\n            prev[2 * b + 1] = (int16_t)o[b].mv_y;",
      "prev[2 * b + 0] = (int16_t)o[b].mv_y;\n            prev[2 * b + 1] = (int16_t)o[b].mv_x;"),
 ]
