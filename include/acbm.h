@@ -83,11 +83,20 @@ typedef struct acbm_geom {
 /* lambda: Lagrange multiplier (Section 2.1); qp: quantisation step of the
  * first ACBM test; alpha, beta, gamma = gamma_num/gamma_den: ACBM thresholds
  * (Section 3.2; the paper's values for 16x16 blocks are 1000, 8, 1/4,
- * Section 4). */
+ * Section 4).
+ * subpel: 0 integer-pel, 1 half-pel precision (Section 2.2's refinement on
+ * the half-pixel grid; Table 1's full search counts the 8 half-pel
+ * positions around the integer winner).  With 1, every vector (results,
+ * predictors, the previous field) is in half-pel units, rates are counted
+ * in those units, half-pel samples of the reference follow H.263's bilinear
+ * interpolation with averages rounded half up, FSBM adds the valid half-pel
+ * neighbours of its integer winner, and the PBM refinement ring is one
+ * half-pel step.  Requires p <= 63 (vectors stay within +-126). */
 typedef struct acbm_params {
     uint32_t lambda, qp;
     uint32_t alpha, beta;
     uint32_t gamma_num, gamma_den;
+    uint32_t subpel;
 } acbm_params;
 
 typedef struct acbm_mv {

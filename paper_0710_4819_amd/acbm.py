@@ -53,7 +53,8 @@ class Geom(C.Structure):
 
 class CParams(C.Structure):
     _fields_ = [("lambda_", C.c_uint32), ("qp", C.c_uint32), ("alpha", C.c_uint32),
-                ("beta", C.c_uint32), ("gamma_num", C.c_uint32), ("gamma_den", C.c_uint32)]
+                ("beta", C.c_uint32), ("gamma_num", C.c_uint32), ("gamma_den", C.c_uint32),
+                ("subpel", C.c_uint32)]
 
 
 class ServeCfg(C.Structure):
@@ -75,16 +76,19 @@ class Job(C.Structure):
 
 @dataclass(frozen=True)
 class Params:
-    """lambda, Qp and the ACBM thresholds; gamma = gamma_num / gamma_den."""
+    """lambda, Qp and the ACBM thresholds; gamma = gamma_num / gamma_den;
+    subpel = 1 for half-pel precision (vectors in half-pel units)."""
     lam: int = 0
     qp: int = 0
     alpha: int = 1000
     beta: int = 8
     gamma_num: int = 1
     gamma_den: int = 4
+    subpel: int = 0
 
     def c(self) -> CParams:
-        return CParams(self.lam, self.qp, self.alpha, self.beta, self.gamma_num, self.gamma_den)
+        return CParams(self.lam, self.qp, self.alpha, self.beta, self.gamma_num, self.gamma_den,
+                       self.subpel)
 
 
 def default_params(block_w: int, block_h: int, lam: int, qp: int | None = None) -> Params:

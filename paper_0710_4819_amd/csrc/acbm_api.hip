@@ -68,7 +68,11 @@ int check_geom(const acbm_geom* g, KGeom* k) {
 int check_params(const acbm_params* prm, const KGeom& k) {
   if (!prm) return fail(ACBM_E_INVAL, "params is NULL");
   if (prm->gamma_den == 0) return fail(ACBM_E_INVAL, "gamma_den is zero");
-  const uint64_t jmax = 255ull * k.bw * k.bh + (uint64_t)prm->lambda * rate_max(k.p);
+  if (prm->subpel > 1) return fail(ACBM_E_INVAL, "subpel must be 0 or 1");
+  if (prm->subpel && k.p > 63)
+    return fail(ACBM_E_RANGE, "half-pel vectors need p <= 63");
+  const uint64_t jmax =
+      255ull * k.bw * k.bh + (uint64_t)prm->lambda * rate_max(prm->subpel ? 2 * k.p : k.p);
   if (jmax >= (1ull << 32)) return fail(ACBM_E_RANGE, "lambda too large: J would not fit 32 bits");
   return ACBM_OK;
 }

@@ -101,9 +101,9 @@ int make_plan(const acbm_job* jobs, size_t njobs, Plan* pl) {
     BatchJob bj{};
     bj.g = k;
     bj.s = window_shape_host(k.bw, k.bh, k.p, sp.R);
-    const uint64_t slack64 = (uint64_t)j.params.lambda * (uint64_t)(rate_max(k.p) - 2);
-    bj.slack = slack64 > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)slack64;
+    bj.slack = fsbm_slack(k.p, j.params);
     bj.lam = j.params.lambda;
+    bj.subpel = j.params.subpel;
     bj.npairs = npairs;
     bj.item0 = c.items;
     c.items += npairs * (uint32_t)k.nb;
@@ -239,6 +239,21 @@ int enqueue_batch(const acbm_job* jobs, size_t njobs, void* ws, hipStream_t st) 
                                c.items, st);
     }
     if (rc) return rc;
+    // half-pel jobs: the SADs around single possible winners, before the
+    // resolve (kernel arguments carry up to 64 pairs' frame pointers)
+    for (size_t q = 0; q < c.jobs.size(); ++q) {
+      const BatchJob& bj = c.jobs[q];
+      if (!bj.subpel) continue;
+      const acbm_job& jj = jobs[c.job_index[q]];
+      char* sl = base + pl.slice[c.job_index[q]];
+      BlockRec* recs = reinterpret_cast<BlockRec*>(sl + fsbm_recs_offset());
+      for (uint32_t p0 = 0; p0 < bj.npairs; p0 += kMaxPairsPerLaunch) {
+        const int n = (int)std::min<uint32_t>(kMaxPairsPerLaunch, bj.npairs - p0);
+        FramePtrs fr{};
+        for (int k = 0; k <= n; ++k) fr.f[k] = jj.frames[p0 + k];
+        if ((rc = launch_half_prep(bj.g, fr, n, recs + (size_t)p0 * bj.g.nb, st))) return rc;
+      }
+    }
     jo += c.jobs.size();
   }
   if ((rc = launch_resolve_batch(all, (int)pl.njob_fsbm, pl.pairs, pl.lds_resolve, st))) return rc;

@@ -242,6 +242,134 @@ __device__ __forceinline__ bool cand_valid(int u, int v, int p, int x0, int y0, 
          y0 + v >= 0 && y0 + v + M <= height;
 }
 
+// ---------------------------------------------------------------------------
+// Half-pel precision.  A half-pel vector (U, V) counts half pixels.  Pixel
+// (i, j) of the block at (x0, y0) is compared with the reference's H.263
+// bilinear sample at (2(x0+i) + U, 2(y0+j) + V): writing that position as
+// (2x + fx, 2y + fy) and A, B, C, D for ref(x, y), ref(x+1, y), ref(x, y+1),
+// ref(x+1, y+1), the sample is A, (A+B+1)/2, (A+C+1)/2 or (A+B+C+D+2)/4 for
+// (fx, fy) = (0,0), (1,0), (0,1), (1,1).  All four cases are
+// (A + B' + C' + D' + 2) / 4 with B' = fx ? B : A, C' = fy ? C : A and
+// D' the pixel at (x + fx, y + fy), which the kernels use branch-free.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool cand_valid_half(int U, int V, int p, int x0, int y0, int N,
+                                                int M, int width, int height) {
+  const int xl = x0 + (U >> 1), yl = y0 + (V >> 1);  // arithmetic shifts: floor(U / 2)
+  return U >= -2 * p && U <= 2 * p && V >= -2 * p && V <= 2 * p && xl >= 0 &&
+         xl + N + (U & 1) <= width && yl >= 0 && yl + M + (V & 1) <= height;
+}
+
+// Per byte (a + b + c + d + 2) >> 2 of four packed u8 words, in two 16-bit
+// lanes per half (4 * 255 + 2 < 2^16, so no lane carries into the next).
+__device__ __forceinline__ uint32_t avg4_u8(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  const uint32_t m = 0x00FF00FFu;
+  const uint32_t lo = (a & m) + (b & m) + (c & m) + (d & m) + 0x00020002u;
+  const uint32_t hi =
+      ((a >> 8) & m) + ((b >> 8) & m) + ((c >> 8) & m) + ((d >> 8) & m) + 0x00020002u;
+  return ((lo >> 2) & m) | (((hi >> 2) & m) << 8);
+}
+
+// Bytes sh .. sh+3 of the 8-byte value lo:hi (sh = 0..4).
+__device__ __forceinline__ uint32_t bytes_at(uint32_t lo, uint32_t hi, uint32_t sh) {
+  return sh >= 4 ? hi : __builtin_amdgcn_alignbyte(hi, lo, sh);
+}
+
+// SAD of one block row against half-pel samples.  d0 and d1 are NC+1 dwords
+// of reference rows y and y+1 starting at the dword that holds byte x (sh =
+// x & 3); c the NC dwords of the current row.
+template <int NC>
+__device__ __forceinline__ uint32_t half_row_sad(const uint32_t (&d0)[NC + 1],
+                                                 const uint32_t (&d1)[NC + 1], uint32_t sh,
+                                                 int fx, int fy, const uint32_t (&c)[NC],
+                                                 uint32_t acc) {
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const uint32_t a = bytes_at(d0[k], d0[k + 1], sh);
+    const uint32_t b = bytes_at(d0[k], d0[k + 1], sh + 1);
+    const uint32_t cc = bytes_at(d1[k], d1[k + 1], sh);
+    const uint32_t dd = bytes_at(d1[k], d1[k + 1], sh + 1);
+    const uint32_t B = fx ? b : a, C = fy ? cc : a, D = fx ? (fy ? dd : b) : (fy ? cc : a);
+    acc = __builtin_amdgcn_sad_u8(avg4_u8(a, B, C, D), c[k], acc);
+  }
+  return acc;
+}
+
+// Sum over aligned groups of G = 8 or 16 lanes, left in every lane of the
+// group: swaps within quads, then the mirror within 8 lanes, then (G = 16)
+// the mirror within 16 lanes.
+template <int G>
+__device__ __forceinline__ uint32_t group_sum(uint32_t x) {
+  static_assert(G == 8 || G == 16, "row sums of 8 or 16 lanes");
+  x += (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+  x += (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+  x += (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  if constexpr (G == 16)
+    x += (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x140, 0xF, 0xF, false);  // row_mirror
+  return x;
+}
+
+// The 8 half-pel neighbours of an integer vector, numbered k = 0..7 in
+// raster order of the 3 x 3 ring without its centre.
+__device__ __forceinline__ void half_ring_offset(int k, int* du, int* dv) {
+  const int dd = k < 4 ? k : k + 1;
+  *du = dd % 3 - 1;
+  *dv = dd / 3 - 1;
+}
+
+// SADs of the 8 half-pel neighbours of (U0, V0) (even: an integer vector)
+// for the block at (x0, y0), by one whole wave from the frames in global
+// memory; 0xFFFF for a neighbour that is not a valid candidate.  Lane item
+// (neighbour, block row); the M lanes of one neighbour are adjacent, so the
+// row sum is a DPP group sum.  Every lane returns the same values.
+template <int N, int M>
+__device__ __forceinline__ void wave_half_sads(const KGeom& g, const uint8_t* __restrict__ cur,
+                                               const uint8_t* __restrict__ ref, int x0, int y0,
+                                               int U0, int V0, uint32_t (&sads)[8]) {
+  constexpr int NC = N / 4;
+  constexpr int PER = 64 / M;  // neighbours per pass
+  const int lane = threadIdx.x & 63;
+  const int j = lane % M;
+  const int last_dw = (g.pitch >> 2) - 1;  // last dword of a row
+#pragma unroll
+  for (int pass = 0; pass < 8 / PER; ++pass) {
+    const int k = pass * PER + lane / M;
+    int du, dv;
+    half_ring_offset(k, &du, &dv);
+    const int U = U0 + du, V = V0 + dv;
+    const bool ok = cand_valid_half(U, V, g.p, x0, y0, N, M, g.width, g.height);
+    uint32_t acc = 0;
+    if (ok) {
+      const int x = x0 + (U >> 1), y = y0 + j + (V >> 1);
+      const int fx = U & 1, fy = V & 1;
+      const uint32_t* r0 = reinterpret_cast<const uint32_t*>(ref + (size_t)y * g.pitch);
+      const uint32_t* r1 = fy ? r0 + (g.pitch >> 2) : r0;
+      const uint32_t* cr = reinterpret_cast<const uint32_t*>(cur + (size_t)(y0 + j) * g.pitch + x0);
+      uint32_t d0[NC + 1], d1[NC + 1], c[NC];
+#pragma unroll
+      for (int q = 0; q <= NC; ++q) {
+        // dwords past the row's end only feed bytes beyond x + N, which no
+        // sample uses; the index is clamped so that nothing is read there
+        const int at = min((x >> 2) + q, last_dw);
+        d0[q] = r0[at];
+        d1[q] = r1[at];
+      }
+#pragma unroll
+      for (int q = 0; q < NC; ++q) c[q] = cr[q];
+      acc = half_row_sad<NC>(d0, d1, (uint32_t)(x & 3), fx, fy, c, 0u);
+    }
+    acc = group_sum<M>(acc);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int kk = pass * PER + q;
+      int eu, ev;
+      half_ring_offset(kk, &eu, &ev);
+      const bool okk = cand_valid_half(U0 + eu, V0 + ev, g.p, x0, y0, N, M, g.width, g.height);
+      const uint32_t s = __builtin_amdgcn_readlane(acc, q * M);
+      sads[kk] = okk ? s : 0xFFFFu;
+    }
+  }
+}
+
 // Number of valid candidates of a block: product of two interval lengths.
 __device__ __forceinline__ uint32_t valid_count(int p, int x0, int y0, int N, int M, int width,
                                                 int height) {

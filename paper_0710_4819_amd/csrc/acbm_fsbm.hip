@@ -326,9 +326,22 @@ __device__ __forceinline__ bool median_pred(const uint32_t* st, int b, int r, in
   return true;
 }
 
+// Key of integer candidate (u, v) with SAD `sad`.  With half-pel precision
+// (HP) the candidate is the half-pel vector (2u, 2v): its rate is taken
+// against the half-pel predictor and it ranks by its half-pel |U|+|V| and
+// its position in the (4p+1)^2 half-pel window, which orders the integer
+// candidates exactly as the integer window does.
+template <bool HP>
+__device__ __forceinline__ uint64_t int_key(uint32_t sad, int u, int v, int p, int px, int py,
+                                            uint32_t lam) {
+  constexpr int s = HP ? 2 : 1;
+  return make_key(sad + lam * (se_bits(s * u - px) + se_bits(s * v - py)), s * u, s * v, s * p);
+}
+
 // Cheapest candidate of one block, computed by a whole wave: the 128-byte
 // record is read with one dword per lane, each listed candidate is priced by
 // its own lane; an overflowed block's row is strided over the lanes.
+template <bool HP>
 __device__ __forceinline__ uint64_t wave_block_argmin(const BlockRec* __restrict__ rec,
                                                       const uint16_t* __restrict__ row, int p,
                                                       int px, int py, uint32_t lam) {
@@ -347,8 +360,7 @@ __device__ __forceinline__ uint64_t wave_block_argmin(const BlockRec* __restrict
       const uint32_t ras = e & 0xFFFFu;
       const uint32_t vq = __umulhi(ras, inv);
       const int v = (int)vq - p, u = (int)(ras - vq * W) - p;
-      const uint32_t j = (e >> 16) + lam * (se_bits(u - px) + se_bits(v - py));
-      const uint64_t key = ((uint64_t)j << 32) | ((uint32_t)(abs(u) + abs(v)) << 16) | ras;
+      const uint64_t key = int_key<HP>(e >> 16, u, v, p, px, py, lam);
       best = key < best ? key : best;
     }
   } else if (n <= (uint32_t)kShort) {
@@ -356,8 +368,7 @@ __device__ __forceinline__ uint64_t wave_block_argmin(const BlockRec* __restrict
     if (k >= 0 && k < (int)n) {
       int u, v;
       window_uv(w & 0xFFFFu, p, &u, &v);
-      const uint32_t j = (w >> 16) + lam * (se_bits(u - px) + se_bits(v - py));
-      best = make_key(j, u, v, p);
+      best = int_key<HP>(w >> 16, u, v, p, px, py, lam);
     }
   } else {
     // The whole row, read as uint4 pieces of 8 SADs: lane k takes pieces
@@ -385,9 +396,7 @@ __device__ __forceinline__ uint64_t wave_block_argmin(const BlockRec* __restrict
         for (int e = 0; e < 8; ++e) {
           const uint32_t sad = (w4[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
           if (sad != 0xFFFFu && pos + e < WW) {
-            const uint32_t j = sad + lam * (se_bits(u - px) + se_bits(v - py));
-            const uint64_t key =
-                ((uint64_t)j << 32) | ((uint32_t)(abs(u) + abs(v)) << 16) | (uint32_t)(pos + e);
+            const uint64_t key = int_key<HP>(sad, u, v, p, px, py, lam);
             best = key < best ? key : best;
           }
           if (++u > p) {
@@ -401,20 +410,85 @@ __device__ __forceinline__ uint64_t wave_block_argmin(const BlockRec* __restrict
   return wave_min_u64(best);
 }
 
+// Half-pel step of block b (whole wave): `key` is the integer winner under
+// the half-pel predictor (px, py); the 8 half-pel positions around it are
+// priced with the same predictor and the cheapest of the nine is the block's
+// result, written straight to `out` (the rate needs the predictor, which is
+// known here).  A block with a single possible winner had its 8 SADs
+// prepared by k_half_prep; the others are computed here.
+__device__ __forceinline__ void half_decide(const KGeom& g, const BlockRec* __restrict__ rec,
+                                            const uint8_t* __restrict__ cur,
+                                            const uint8_t* __restrict__ ref, int b, int px,
+                                            int py, uint32_t lam, uint64_t key,
+                                            acbm_block_result* __restrict__ out, uint32_t* st) {
+  const int p = g.p, lane = threadIdx.x & 63;
+  int U0 = 0, V0 = 0;
+  window_uv((uint32_t)(key & 0xFFFFu), 2 * p, &U0, &V0);
+  const int r = b / g.bx, c = b - r * g.bx, x0 = c * g.bw, y0 = r * g.bh;
+  uint32_t sads[8];
+  if (rec->count == 1) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sads[k] = (rec->e[1 + k / 2] >> (16 * (k & 1))) & 0xFFFFu;
+  } else if (g.bw == 16 && g.bh == 16) {
+    wave_half_sads<16, 16>(g, cur, ref, x0, y0, U0, V0, sads);
+  } else if (g.bw == 16) {
+    wave_half_sads<16, 8>(g, cur, ref, x0, y0, U0, V0, sads);
+  } else if (g.bh == 16) {
+    wave_half_sads<8, 16>(g, cur, ref, x0, y0, U0, V0, sads);
+  } else {
+    wave_half_sads<8, 8>(g, cur, ref, x0, y0, U0, V0, sads);
+  }
+  uint64_t best = key;
+  uint32_t nh = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (sads[k] == 0xFFFFu) continue;
+    int du, dv;
+    half_ring_offset(k, &du, &dv);
+    const int U = U0 + du, V = V0 + dv;
+    const uint64_t kk = make_key(sads[k] + lam * (se_bits(U - px) + se_bits(V - py)), U, V, 2 * p);
+    best = kk < best ? kk : best;
+    ++nh;
+  }
+  int U = 0, V = 0;
+  window_uv((uint32_t)(best & 0xFFFFu), 2 * p, &U, &V);
+  const uint32_t rate = se_bits(U - px) + se_bits(V - py);
+  const uint32_t j = (uint32_t)(best >> 32), sad = j - lam * rate;
+  if (lane == 0) {
+    acbm_block_result res;
+    res.mv.x = (int16_t)U;
+    res.mv.y = (int16_t)V;
+    res.sad = sad;
+    res.j = j;
+    res.rate_bits = rate;
+    res.cands = valid_count(p, x0, y0, g.bw, g.bh, g.width, g.height) + nh;
+    res.mode = ACBM_MODE_FSBM;
+    res.intra_x = rec->intra_x;
+    *out = res;
+    *st = (sad << 16) | pack_mv(U, V);
+  }
+}
+
 // FSBM resolve of one frame pair by the whole group.  `st` is the pair's
-// decision state (LDS or workspace); `pending` a shared flag.
+// decision state (LDS or workspace); `pending` a shared flag.  HP: half-pel
+// precision, vectors in half-pel units; cur and ref are then the pair's
+// frames (the half-pel step reads them).
+template <bool HP>
 __device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __restrict__ recs,
                                              const uint16_t* __restrict__ ovf,
                                              acbm_block_result* __restrict__ out, uint32_t lam,
-                                             uint32_t* st, int* pending_flag) {
+                                             uint32_t* st, int* pending_flag,
+                                             const uint8_t* __restrict__ cur,
+                                             const uint8_t* __restrict__ ref) {
   int& pending = *pending_flag;
   const int p = g.p, W = 2 * p + 1, nb = g.nb, bx = g.bx;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
 
   // blocks with a single possible winner are decided without a predictor
+  // (not with half-pel precision: their half-pel step needs it)
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
     uint32_t w = kOpen;
-    if (recs[b].count == 1) {
+    if (!HP && recs[b].count == 1) {
       const uint32_t e = recs[b].e[0];
       int u, v;
       window_uv(e & 0xFFFFu, p, &u, &v);
@@ -447,7 +521,11 @@ __device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __r
         const int bb = base + k;
         const int qx = __shfl(px, k, 64), qy = __shfl(py, k, 64);
         const uint64_t key =
-            wave_block_argmin(recs + bb, ovf + (size_t)bb * ovf_stride(p), p, qx, qy, lam);
+            wave_block_argmin<HP>(recs + bb, ovf + (size_t)bb * ovf_stride(p), p, qx, qy, lam);
+        if (HP) {
+          half_decide(g, recs + bb, cur, ref, bb, qx, qy, lam, key, out + bb, st + bb);
+          continue;
+        }
         int u = 0, v = 0;
         uint32_t sad = 0;
         if (key != ~0ull) {
@@ -464,6 +542,7 @@ __device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __r
     __syncthreads();
     if (!again) break;
   }
+  if (HP) return;  // every result was written when its block was decided
 
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
     const int r = b / bx, c = b - r * bx;
@@ -489,15 +568,44 @@ __device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __r
 // One workgroup per frame pair.  The state lives in LDS when it fits
 // (st_global == nullptr), else in a workspace array; either way only this
 // workgroup touches it.
+template <bool HP>
 __global__ void __launch_bounds__(1024)
 k_resolve(const KGeom g, const BlockRec* __restrict__ recs, const uint16_t* __restrict__ ovf,
-          acbm_block_result* __restrict__ out, uint32_t lam, uint32_t* st_global) {
+          acbm_block_result* __restrict__ out, uint32_t lam, uint32_t* st_global,
+          const FramePtrs fr) {
   extern __shared__ uint32_t st_lds[];
   __shared__ int pending;
   const int pair = blockIdx.x;
-  resolve_pair(g, recs + (size_t)pair * g.nb, ovf + (size_t)pair * g.nb * ovf_stride(g.p),
-               out + (size_t)pair * g.nb, lam,
-               st_global ? st_global + (size_t)pair * g.nb : st_lds, &pending);
+  resolve_pair<HP>(g, recs + (size_t)pair * g.nb, ovf + (size_t)pair * g.nb * ovf_stride(g.p),
+                   out + (size_t)pair * g.nb, lam,
+                   st_global ? st_global + (size_t)pair * g.nb : st_lds, &pending,
+                   HP ? fr.f[pair + 1] : nullptr, HP ? fr.f[pair] : nullptr);
+}
+
+// Half-pel SADs around the single possible winner of every block that has
+// one (the 92 % or so of blocks the resolve could otherwise decide without
+// a predictor): one wave per (pair, block), written to the free slots
+// e[1..4] of its record (8 u16, ring order).  These do not depend on the
+// predictor, so they are computed here, in parallel, off the resolve's
+// sequential path.
+template <int N, int M>
+__global__ void __launch_bounds__(256)
+k_half_prep(const KGeom g, const FramePtrs fr, int npairs, BlockRec* __restrict__ recs) {
+  const int lane = threadIdx.x & 63;
+  const size_t item = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= (size_t)npairs * g.nb) return;
+  const int pair = (int)(item / (size_t)g.nb), b = (int)(item % (size_t)g.nb);
+  BlockRec* rec = recs + item;
+  if (rec->count != 1) return;  // the same word for the whole wave
+  int u = 0, v = 0;
+  window_uv(rec->e[0] & 0xFFFFu, g.p, &u, &v);
+  const int r = b / g.bx, c = b - r * g.bx;
+  uint32_t sads[8];
+  wave_half_sads<N, M>(g, fr.f[pair + 1], fr.f[pair], c * N, r * M, 2 * u, 2 * v, sads);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rec->e[1 + q] = sads[2 * q] | (sads[2 * q + 1] << 16);
+  }
 }
 
 // The resolves of every pair of one batch class: one workgroup per pair.
@@ -518,9 +626,14 @@ k_resolve_batch(const BatchJob* __restrict__ jobs, int njobs) {
   const BatchJob& J = jobs[j];
   const KGeom g = J.g;
   const int pair = (int)(wg - J.pair0);
-  resolve_pair(g, J.recs + (size_t)pair * g.nb, J.ovf + (size_t)pair * g.nb * ovf_stride(g.p),
-               J.out + (size_t)pair * g.nb, J.lam,
-               J.mv_ws ? J.mv_ws + (size_t)pair * g.nb : st_lds, &pending);
+  const BlockRec* recs = J.recs + (size_t)pair * g.nb;
+  const uint16_t* ovf = J.ovf + (size_t)pair * g.nb * ovf_stride(g.p);
+  acbm_block_result* out = J.out + (size_t)pair * g.nb;
+  uint32_t* st = J.mv_ws ? J.mv_ws + (size_t)pair * g.nb : st_lds;
+  if (__builtin_amdgcn_readfirstlane(J.subpel))
+    resolve_pair<true>(g, recs, ovf, out, J.lam, st, &pending, J.frames[pair + 1], J.frames[pair]);
+  else
+    resolve_pair<false>(g, recs, ovf, out, J.lam, st, &pending, nullptr, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -704,6 +817,35 @@ size_t fsbm_ws_bytes(const KGeom& g, uint32_t npairs) {
          align256((size_t)npairs * g.nb * ovf_row_bytes(g)) + mv_bytes;
 }
 
+// Pruning slack of the window search: with R >= 2 everywhere and R <= Rmax,
+// a candidate can only win when SAD <= SAD_min + lambda*(Rmax - 2).  With
+// half-pel precision the integer candidates are priced in half-pel units,
+// so Rmax is that of |mvd| <= 4p.
+uint32_t fsbm_slack(int p, const acbm_params& prm) {
+  const int rmax = prm.subpel ? rate_max(2 * p) : rate_max(p);
+  const uint64_t s = (uint64_t)prm.lambda * (uint64_t)(rmax - 2);
+  return s > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)s;
+}
+
+int launch_half_prep(const KGeom& g, const FramePtrs& fr, int npairs, BlockRec* recs,
+                     hipStream_t st) {
+  const size_t items = (size_t)npairs * g.nb;
+  const dim3 grid((unsigned)((items + 3) / 4)), block(256);
+  ProfScope ps("half", st);
+  if (g.bw == 16 && g.bh == 16)
+    hipLaunchKernelGGL((k_half_prep<16, 16>), grid, block, 0, st, g, fr, npairs, recs);
+  else if (g.bw == 16 && g.bh == 8)
+    hipLaunchKernelGGL((k_half_prep<16, 8>), grid, block, 0, st, g, fr, npairs, recs);
+  else if (g.bw == 8 && g.bh == 16)
+    hipLaunchKernelGGL((k_half_prep<8, 16>), grid, block, 0, st, g, fr, npairs, recs);
+  else if (g.bw == 8 && g.bh == 8)
+    hipLaunchKernelGGL((k_half_prep<8, 8>), grid, block, 0, st, g, fr, npairs, recs);
+  else
+    return fail(ACBM_E_UNSUPPORTED, "block size must be 8 or 16 in each direction");
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ACBM_OK : hip_fail(e, "launching the half-pel preparation");
+}
+
 int launch_fsbm(const KGeom& g, const acbm_params& prm, const uint8_t* const* frames,
                 uint32_t npairs, void* ws, size_t ws_bytes, acbm_block_result* out,
                 hipStream_t st) {
@@ -718,8 +860,8 @@ int launch_fsbm(const KGeom& g, const acbm_params& prm, const uint8_t* const* fr
                                     base + align256(sizeof(WsHeader)) +
                                     align256((size_t)npairs * g.nb * sizeof(BlockRec)) +
                                     align256((size_t)npairs * g.nb * ovf_row_bytes(g)));
-  const uint64_t slack64 = (uint64_t)prm.lambda * (uint64_t)(rate_max(g.p) - 2);
-  const uint32_t slack = slack64 > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)slack64;
+  const bool hp = prm.subpel != 0;
+  const uint32_t slack = fsbm_slack(g.p, prm);
   for (uint32_t p0 = 0; p0 < npairs; p0 += kMaxPairsPerLaunch) {
     const int n = (int)std::min<uint32_t>(kMaxPairsPerLaunch, npairs - p0);
     FramePtrs fr{};
@@ -728,14 +870,20 @@ int launch_fsbm(const KGeom& g, const acbm_params& prm, const uint8_t* const* fr
     uint16_t* o = ovf + (size_t)p0 * g.nb * (ovf_row_bytes(g) / 2);
     int rc = launch_search<false>(g, fr, n, nullptr, r, o, slack, st);
     if (rc) return rc;
+    if (hp && (rc = launch_half_prep(g, fr, n, r, st))) return rc;
     const size_t rlds = mv_in_lds ? (size_t)g.nb * sizeof(uint32_t) : 0;
+    const void* fn = hp ? (const void*)k_resolve<true> : (const void*)k_resolve<false>;
     if (rlds > 64 * 1024)
-      (void)hipFuncSetAttribute((const void*)k_resolve, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)rlds);
+      (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rlds);
     ProfScope ps("resolve", st);
-    hipLaunchKernelGGL(k_resolve, dim3(n), dim3(1024), rlds, st, g, r, o,
-                       out + (size_t)p0 * g.nb, prm.lambda,
-                       mv_in_lds ? nullptr : mv_ws + (size_t)p0 * g.nb);
+    if (hp)
+      hipLaunchKernelGGL(k_resolve<true>, dim3(n), dim3(1024), rlds, st, g, r, o,
+                         out + (size_t)p0 * g.nb, prm.lambda,
+                         mv_in_lds ? nullptr : mv_ws + (size_t)p0 * g.nb, fr);
+    else
+      hipLaunchKernelGGL(k_resolve<false>, dim3(n), dim3(1024), rlds, st, g, r, o,
+                         out + (size_t)p0 * g.nb, prm.lambda,
+                         mv_in_lds ? nullptr : mv_ws + (size_t)p0 * g.nb, fr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "launching the FSBM resolve");
   }

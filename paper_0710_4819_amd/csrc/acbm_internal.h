@@ -64,6 +64,7 @@ struct BatchJob {
   uint32_t* mv_ws;               // [npairs][nb] resolve state if it does not fit in LDS, else null
   uint32_t slack, lam, npairs;
   uint32_t item0, pair0;
+  uint32_t subpel;               // half-pel precision (vectors in half-pel units)
 };
 
 // Launch plan of the window search for one (N, M, p).
@@ -85,6 +86,7 @@ constexpr uint32_t kStatusSpinTimeout = 1;
 
 size_t align256(size_t x);
 int rate_max(int p);  // 2 * se_bits(2p)
+uint32_t fsbm_slack(int p, const acbm_params& prm);
 int lds_limit();      // dynamic LDS bytes a workgroup may use on this device
 
 // Set the thread's error detail and return `code`.
@@ -131,6 +133,10 @@ int launch_fsbm(const KGeom& g, const acbm_params& prm, const uint8_t* const* fr
                 hipStream_t s);
 // Window search with an explicit plan, over `npairs` pairs of one job
 // (kTable = false: BlockRec + overflow rows).
+// Half-pel SADs around the single possible winner of the blocks that have
+// one (records of `npairs` pairs), before a half-pel resolve.
+int launch_half_prep(const KGeom& g, const FramePtrs& fr, int npairs, BlockRec* recs,
+                     hipStream_t st);
 int launch_search_plan(const KGeom& g, const SearchPlan& pl, const uint8_t* const* frames,
                        int npairs, BlockRec* recs, uint16_t* ovf, uint32_t slack,
                        hipStream_t s);

@@ -206,20 +206,6 @@ __device__ __forceinline__ void park_columns(uint32_t* __restrict__ ring, const 
   }
 }
 
-// Sum over aligned groups of G = 8 or 16 lanes, left in every lane of the
-// group: swaps within quads, then the mirror within 8 lanes, then (G = 16)
-// the mirror within 16 lanes.
-template <int G>
-__device__ __forceinline__ uint32_t group_sum(uint32_t x) {
-  static_assert(G == 8 || G == 16, "row sums of 8 or 16 lanes");
-  x += (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
-  x += (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
-  x += (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x141, 0xF, 0xF, false);  // row_half_mirror
-  if constexpr (G == 16)
-    x += (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x140, 0xF, 0xF, false);  // row_mirror
-  return x;
-}
-
 // ---------------------------------------------------------------------------
 // PBM: SADs of the 3 x 4 neighbourhood (u-1..u+2) x (v-1..v+1) of every
 // predictor candidate.  nbr[ci][dv] holds four u16 SADs, columns u-1+i in
@@ -275,6 +261,72 @@ __device__ __forceinline__ void pbm_neighbourhoods(const uint32_t* __restrict__ 
       for (int dv = 0; dv < 3; ++dv) nbr[ci][dv] = acc[dv];
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Half-pel precision: SADs against H.263 half-pel samples, read from the
+// ring.  Candidate (U, V) (half pixels) reads, for block row j, window row
+// (V >> 1) + p + j (and the next one when V is odd) from byte
+// (U >> 1) - u_lo of the block's first window column on (and the next byte
+// when U is odd).  Valid candidates stay inside the window: |U|, |V| <= 2p.
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ uint32_t ring_half_row(const uint32_t* __restrict__ ring,
+                                                  const RingShape& w, int cb0,
+                                                  const uint32_t* __restrict__ cd, int U, int V,
+                                                  int j) {
+  constexpr int NC = N / 4;
+  const int xoff = (U >> 1) - w.s.u_lo;
+  const int col = (cb0 + (xoff >> 2)) & (w.cw - 1);
+  const int row0 = (V >> 1) + w.s.p + j;
+  const uint32_t* r0 = ring + row0 * w.stride + col;
+  const uint32_t* r1 = (V & 1) ? r0 + w.stride : r0;
+  uint32_t d0[NC + 1], d1[NC + 1], c[NC];
+#pragma unroll
+  for (int q = 0; q <= NC; ++q) {
+    d0[q] = r0[q];
+    d1[q] = r1[q];
+  }
+#pragma unroll
+  for (int q = 0; q < NC; ++q) c[q] = cd[j * NC + q];
+  return half_row_sad<NC>(d0, d1, (uint32_t)(xoff & 3), U & 1, V & 1, c, 0u);
+}
+
+// Half-pel SADs of the predictor candidates (cu, cv) into sadh: one lane
+// per (candidate, block row), rows summed within groups of M lanes.
+template <int N, int M, int NT>
+__device__ __forceinline__ void pbm_half_sads(const uint32_t* __restrict__ ring,
+                                              const RingShape& w, int cb0,
+                                              const uint32_t* __restrict__ cd, const int16_t* cu,
+                                              const int16_t* cv, int np, uint32_t* sadh) {
+  constexpr int PER = NT / M;
+  const int j = threadIdx.x % M;
+  for (int base = 0; base < np; base += PER) {
+    const int ci = base + (int)threadIdx.x / M;
+    uint32_t acc = 0;
+    if (ci < np) acc = ring_half_row<N>(ring, w, cb0, cd, cu[ci], cv[ci], j);
+    acc = group_sum<M>(acc);
+    if (ci < np && j == 0) sadh[ci] = acc;
+  }
+}
+
+// Half-pel SADs of the ring neighbours k (bit k of `mask`) of (U0, V0) into
+// sadr[k], by the first 8*M threads (whole waves).
+template <int N, int M>
+__device__ __forceinline__ void ring_half_sads(const uint32_t* __restrict__ ring,
+                                               const RingShape& w, int cb0,
+                                               const uint32_t* __restrict__ cd, int U0, int V0,
+                                               uint32_t mask, uint32_t* sadr) {
+  if ((int)threadIdx.x >= 8 * M) return;
+  const int k = (int)threadIdx.x / M, j = (int)threadIdx.x % M;
+  uint32_t acc = 0;
+  if ((mask >> k) & 1u) {
+    int du, dv;
+    half_ring_offset(k, &du, &dv);
+    acc = ring_half_row<N>(ring, w, cb0, cd, U0 + du, V0 + dv, j);
+  }
+  acc = group_sum<M>(acc);
+  if (j == 0) sadr[k] = acc;
 }
 
 // Minimum over lanes 0..15 of a 64-bit key, left in each of those lanes
@@ -362,14 +414,17 @@ __device__ __forceinline__ void task_sads_ring(const uint32_t* __restrict__ ring
   }
 }
 
-template <int N, int M, int R>
+// HP: the integer candidates are priced as half-pel vectors (2u, 2v) against
+// the half-pel predictor, and keyed in the (4p+1)^2 half-pel window.
+template <int N, int M, int R, bool HP>
 __device__ __forceinline__ uint64_t critical_search(const uint32_t* __restrict__ ring,
                                                    const RingShape& w, int cb0,
                                                    const uint32_t* __restrict__ cd,
                                                    const ValidBox& vbox, int px, int py,
                                                    uint32_t lam, uint64_t* red) {
+  constexpr int S = HP ? 2 : 1;
   const WindowShape& s = w.s;
-  const int p = s.p, W = 2 * p + 1;
+  const int p = s.p, W = 2 * S * p + 1;
   const int tasks = s.quads * s.groups;
   uint64_t lbest = ~0ull;
 #pragma unroll 1
@@ -381,12 +436,12 @@ __device__ __forceinline__ uint64_t critical_search(const uint32_t* __restrict__
     mask_invalid<R>(acc, vbox, u0, v0);
     uint32_t ru[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) ru[i] = lam * se_bits(u0 + i - px);
+    for (int i = 0; i < 4; ++i) ru[i] = lam * se_bits(S * (u0 + i) - px);
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
       const int v = v0 + rr;
-      const uint32_t rv = lam * se_bits(v - py);
-      const uint32_t rasb = (uint32_t)((v + p) * W + p);
+      const uint32_t rv = lam * se_bits(S * v - py);
+      const uint32_t rasb = (uint32_t)((S * v + S * p) * W + S * p);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const uint32_t sad = field16(acc[rr], i);
@@ -394,7 +449,8 @@ __device__ __forceinline__ uint64_t critical_search(const uint32_t* __restrict__
         const uint64_t key =
             sad == 0xFFFFu ? ~0ull
                            : ((uint64_t)(sad + ru[i] + rv) << 32) |
-                                 ((uint32_t)(abs(u) + abs(v)) << 16) | (rasb + (uint32_t)u);
+                                 ((uint32_t)(S * (abs(u) + abs(v))) << 16) |
+                                 (rasb + (uint32_t)(S * u));
         lbest = key < lbest ? key : lbest;
       }
     }
@@ -418,7 +474,7 @@ __device__ __forceinline__ void write_result(acbm_block_result* out, uint32_t* w
   store_word(word, kReady | pack_mv(u, v));
 }
 
-template <int N, int M, int R, int NT>
+template <int N, int M, int R, int NT, bool HP>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ACBM_PRED_WAVES)))
 k_predictive(const PredArgs a) {
   extern __shared__ uint32_t ring[];
@@ -429,6 +485,7 @@ k_predictive(const PredArgs a) {
   __shared__ uint32_t curd[2][D];
   __shared__ int16_t cu[kMaxCands], cv[kMaxCands];
   __shared__ uint64_t nbr[kMaxCands][3];
+  __shared__ uint32_t sadh[kMaxCands], sadr[8];  // half-pel SADs: predictors, ring
   __shared__ int sh_row, sh_abort, sh_np, sh_px, sh_py;
   __shared__ uint32_t sh_intra;
   __shared__ uint16_t sh_left;
@@ -436,7 +493,7 @@ k_predictive(const PredArgs a) {
   const KGeom& g = a.g;
   const RingShape& w = a.w;
   const int p = g.p, bx = g.bx, by = g.by, nb = g.nb;
-  const int W = 2 * p + 1;
+  const int W = 2 * (HP ? 2 : 1) * p + 1;  // key raster width (half-pel window with HP)
   const uint32_t total_rows = (uint32_t)a.npairs * by;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -537,7 +594,8 @@ k_predictive(const PredArgs a) {
         // predictor set: valid candidates, first occurrence of each vector
         const int u = mv_x(val), v = mv_y(val);
         const bool ok = lane < 14 && val != kMvUnset &&
-                        cand_valid(u, v, p, x0, y0, N, M, g.width, g.height);
+                        (HP ? cand_valid_half(u, v, p, x0, y0, N, M, g.width, g.height)
+                            : cand_valid(u, v, p, x0, y0, N, M, g.width, g.height));
         const uint32_t tagged = ok ? (uint32_t)val : 0xFFFFFFFFu;
         bool dup = false;
 #pragma unroll
@@ -595,7 +653,10 @@ k_predictive(const PredArgs a) {
         cand_u = cu[lane];
         cand_v = cv[lane];
       }
-      pbm_neighbourhoods<N, M, NT>(ring, w, cb0, cd, cu, cv, np, nbr);
+      if constexpr (HP)
+        pbm_half_sads<N, M, NT>(ring, w, cb0, cd, cu, cv, np, sadh);
+      else
+        pbm_neighbourhoods<N, M, NT>(ring, w, cb0, cd, cu, cv, np, nbr);
       __syncthreads();
 
       // ---- C: PBM steps 2 and 3, ACBM decision (every wave, redundantly, so
@@ -603,10 +664,11 @@ k_predictive(const PredArgs a) {
       int crit_n = 0;  // candidates PBM evaluated, if the block is critical
       {
         const int u = cand_u, v = cand_v;
+        constexpr int S = HP ? 2 : 1;  // key window of half-pel vectors with HP
         uint64_t key = ~0ull;
         if (lane < np) {
-          const uint32_t sad = field16(nbr[lane][1], 1);
-          key = make_key(sad + a.lam * (se_bits(u - px) + se_bits(v - py)), u, v, p);
+          const uint32_t sad = HP ? sadh[lane] : field16(nbr[lane][1], 1);
+          key = make_key(sad + a.lam * (se_bits(u - px) + se_bits(v - py)), u, v, S * p);
         }
         // at most 14 predictors and 8 neighbours: minima over lanes 0..15
         const uint64_t k2 = lane0_u64(row_min_u64(key));
@@ -616,14 +678,21 @@ k_predictive(const PredArgs a) {
         const int dd = lane < 4 ? lane : lane + 1;  // skip the centre
         const int du = dd % 3 - 1, dv = dd / 3 - 1;
         const int un = bu + du, vn = bv + dv;
-        bool add = lane < 8 && cand_valid(un, vn, p, x0, y0, N, M, g.width, g.height);
+        bool add = lane < 8 && (HP ? cand_valid_half(un, vn, p, x0, y0, N, M, g.width, g.height)
+                                   : cand_valid(un, vn, p, x0, y0, N, M, g.width, g.height));
         const uint32_t mine = ((uint32_t)(u & 0xFFFF) << 16) | (uint32_t)(v & 0xFFFF);
         const uint32_t want = ((uint32_t)(un & 0xFFFF) << 16) | (uint32_t)(vn & 0xFFFF);
         for (int q = 0; q < np; ++q) add &= __builtin_amdgcn_readlane(mine, q) != want;
+        if constexpr (HP) {
+          // the ring's half-pel SADs: a second pass (every wave computed the
+          // same ring, so the mask is uniform), shared through LDS
+          ring_half_sads<N, M>(ring, w, cb0, cd, bu, bv, (uint32_t)__ballot(add), sadr);
+          __syncthreads();
+        }
         uint64_t key3 = ~0ull;
         if (add) {
-          const uint32_t sad = field16(nbr[bi][dv + 1], du + 1);
-          key3 = make_key(sad + a.lam * (se_bits(un - px) + se_bits(vn - py)), un, vn, p);
+          const uint32_t sad = HP ? sadr[lane] : field16(nbr[bi][dv + 1], du + 1);
+          key3 = make_key(sad + a.lam * (se_bits(un - px) + se_bits(vn - py)), un, vn, S * p);
         }
         const uint64_t k3 = lane0_u64(row_min_u64(key3));
         const uint32_t n = (uint32_t)(np + __builtin_popcountll(__ballot(add)));
@@ -658,13 +727,35 @@ k_predictive(const PredArgs a) {
       if (crit_n) {  // uniform: every wave took the same decision
         const ValidBox vbox = valid_box(p, x0, y0, N, M, g.width, g.height);
         __builtin_amdgcn_s_setprio(3);  // the full search is on this row's critical path
-        const uint64_t best = critical_search<N, M, R>(ring, w, cb0, cd, vbox, px, py, a.lam, red);
+        uint64_t best = critical_search<N, M, R, HP>(ring, w, cb0, cd, vbox, px, py, a.lam, red);
+        uint32_t nh = 0;
+        if constexpr (HP) {
+          // the 8 half-pel positions around the integer winner
+          const int hp = 2 * p, ras0 = (int)(best & 0xFFFFu);
+          const int U0 = ras0 % W - hp, V0 = ras0 / W - hp;
+          int du, dv;
+          half_ring_offset(lane & 7, &du, &dv);
+          const bool ok = lane < 8 && cand_valid_half(U0 + du, V0 + dv, p, x0, y0, N, M,
+                                                      g.width, g.height);
+          const uint64_t m = __ballot(ok);
+          ring_half_sads<N, M>(ring, w, cb0, cd, U0, V0, (uint32_t)m, sadr);
+          __syncthreads();
+          uint64_t kk = ~0ull;
+          if (ok)
+            kk = make_key(sadr[lane] + a.lam * (se_bits(U0 + du - px) + se_bits(V0 + dv - py)),
+                          U0 + du, V0 + dv, hp);
+          kk = lane0_u64(row_min_u64(kk));
+          best = kk < best ? kk : best;
+          nh = (uint32_t)__builtin_popcountll(m);
+        }
         __builtin_amdgcn_s_setprio(0);
         if (threadIdx.x == 0) {
           const int ras = (int)(best & 0xFFFFu);
-          const int u = ras % W - p, v = ras / W - p;
+          const int sp = (HP ? 2 : 1) * p;
+          const int u = ras % W - sp, v = ras / W - sp;
           const uint32_t rate = se_bits(u - px) + se_bits(v - py);
-          const uint32_t cands = (uint32_t)crit_n + valid_count(p, x0, y0, N, M, g.width, g.height);
+          const uint32_t cands =
+              (uint32_t)crit_n + valid_count(p, x0, y0, N, M, g.width, g.height) + nh;
           write_result(a.out + (size_t)t * nb + b, words + b, u, v, (uint32_t)(best >> 32), rate,
                        a.lam, cands, ACBM_MODE_CRITICAL, intra);
           sh_left = pack_mv(u, v);
@@ -725,13 +816,13 @@ static int device_cus() {
   return cus;
 }
 
-template <int N, int M, int NT>
+template <int N, int M, int NT, bool HP = false>
 static int launch_pred_nmt(const PredArgs& a, int R, size_t lds,
                            hipStream_t st) {
   switch (R) {
 #define ACBM_CASE(RR)                                                                      \
   case RR: {                                                                               \
-    const void* fn = (const void*)k_predictive<N, M, RR, NT>;                              \
+    const void* fn = (const void*)k_predictive<N, M, RR, NT, HP>;                          \
     if (lds > 64 * 1024)                                                                   \
       (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
     int per_cu = 0;                                                                        \
@@ -742,7 +833,7 @@ static int launch_pred_nmt(const PredArgs& a, int R, size_t lds,
     const int grid = (int)std::min<size_t>((size_t)device_cus() * per_cu,                  \
                                            (size_t)a.npairs * a.g.by);                     \
     ProfScope ps("predictive", st);                                                        \
-    hipLaunchKernelGGL((k_predictive<N, M, RR, NT>), dim3(grid), dim3(NT), lds, st, a);     \
+    hipLaunchKernelGGL((k_predictive<N, M, RR, NT, HP>), dim3(grid), dim3(NT), lds, st, a); \
     break;                                                                                 \
   }
     ACBM_PRED_R_LIST(ACBM_CASE)
@@ -754,8 +845,10 @@ static int launch_pred_nmt(const PredArgs& a, int R, size_t lds,
   return e == hipSuccess ? ACBM_OK : hip_fail(e, "launching the predictive search");
 }
 
+// Half-pel precision runs with 256-thread walkers only.
 template <int N, int M>
-static int launch_pred_nm(const PredArgs& a, int R, int nt, size_t lds, hipStream_t st) {
+static int launch_pred_nm(const PredArgs& a, int R, int nt, size_t lds, bool hp, hipStream_t st) {
+  if (hp) return launch_pred_nmt<N, M, 256, true>(a, R, lds, st);
   if (nt == 128) return launch_pred_nmt<N, M, 128>(a, R, lds, st);
   if (nt == 512) return launch_pred_nmt<N, M, 512>(a, R, lds, st);
   return launch_pred_nmt<N, M, 256>(a, R, lds, st);
@@ -797,7 +890,8 @@ int launch_predictive(const KGeom& g, const acbm_params& prm, int algo,
                       const uint8_t* const* frames, uint32_t npairs, const acbm_mv* prev_field,
                       void* ws, size_t ws_bytes, acbm_block_result* out, hipStream_t st) {
   if (ws_bytes < predictive_ws_bytes(g, npairs)) return fail(ACBM_E_NOMEM, "workspace too small");
-  const int nt = row_threads();
+  const bool hp = prm.subpel != 0;
+  const int nt = hp ? 256 : row_threads();
   const int R = pick_rows(g, nt);
   if (!R) return fail(ACBM_E_UNSUPPORTED, "search window too large for the predictive kernel");
   const uint32_t per = std::min<uint32_t>(npairs, kMaxPairsPerLaunch);
@@ -846,10 +940,10 @@ int launch_predictive(const KGeom& g, const acbm_params& prm, int algo,
     if (e != hipSuccess) return hip_fail(e, "launching the predictive setup");
 
     int rc;
-    if (g.bw == 16 && g.bh == 16) rc = launch_pred_nm<16, 16>(a, R, nt, lds, st);
-    else if (g.bw == 16 && g.bh == 8) rc = launch_pred_nm<16, 8>(a, R, nt, lds, st);
-    else if (g.bw == 8 && g.bh == 16) rc = launch_pred_nm<8, 16>(a, R, nt, lds, st);
-    else rc = launch_pred_nm<8, 8>(a, R, nt, lds, st);
+    if (g.bw == 16 && g.bh == 16) rc = launch_pred_nm<16, 16>(a, R, nt, lds, hp, st);
+    else if (g.bw == 16 && g.bh == 8) rc = launch_pred_nm<16, 8>(a, R, nt, lds, hp, st);
+    else if (g.bw == 8 && g.bh == 16) rc = launch_pred_nm<8, 16>(a, R, nt, lds, hp, st);
+    else rc = launch_pred_nm<8, 8>(a, R, nt, lds, hp, st);
     if (rc) return rc;
   }
   return ACBM_OK;

@@ -46,7 +46,7 @@ def same(gpu: np.ndarray, ref: np.ndarray, what: str):
 
 def oparams(p: acbm.Params) -> oracle.Params:
     return oracle.Params(lam=p.lam, qp=p.qp, alpha=p.alpha, beta=p.beta,
-                         gamma_num=p.gamma_num, gamma_den=p.gamma_den)
+                         gamma_num=p.gamma_num, gamma_den=p.gamma_den, subpel=p.subpel)
 
 
 def frames_noise(h, w, seed, hi=256):
