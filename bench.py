@@ -67,7 +67,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--frames", type=int, default=60)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", choices=["fsbm", "acbm", "batch", "serve"], default=None,
+    ap.add_argument("--only", choices=["fsbm", "acbm", "halfpel", "batch", "serve"], default=None,
                     help="run only one leg (profiling runs)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-sequence leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-requests leg")
@@ -171,6 +171,48 @@ def batched_leg(torch, acbm, synth, dev, reps=5):
             "tuned_rows": {f"{k[0]}x{k[1]}_p{k[2]}": v for k, v in tuned.items()}}
 
 
+def halfpel_leg(torch, acbm, frames, prm, stream, steps):
+    """FSBM and ACBM with half-pel precision on the same sequence (Table 1
+    counts the 8 half-pel positions of the full search): device time per
+    step and per kernel, candidates per block."""
+    import dataclasses
+    hp = dataclasses.replace(prm, subpel=1)
+    dev = frames[0].device
+    out = {}
+    for name, algo in (("fsbm", acbm.ALGO_FSBM), ("acbm", acbm.ALGO_ACBM)):
+        b = acbm.Batch(dev)
+        res = b.add(frames, 16, 16, 32, hp, algo)
+        ws = torch.empty(max(256, b.workspace_size()), dtype=torch.uint8, device=dev)
+        b.run(ws, stream)  # warm-up
+        torch.cuda.synchronize()
+        acbm.profile_enable(True)
+        acbm.profile_reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            b.run(ws, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        kern = {}
+        for k in ("search", "half", "resolve", "predictive"):
+            ms, n = acbm.profile_read(k)
+            if n:
+                kern[k + "_ms_per_launch"] = ms / n
+        acbm.profile_enable(False)
+        if algo == acbm.ALGO_ACBM:
+            assert acbm.workspace_status(ws, stream) == 0, "half-pel ACBM dependency wait timed out"
+        r = acbm.to_numpy(res)
+        ms = e0.elapsed_time(e1) / steps
+        npairs = len(frames) - 1
+        out[name] = {"ms": ms, "frames_per_s": npairs / (ms / 1e3),
+                     "cands_per_block": float(r["cands"].mean()),
+                     "evals": int(r["cands"].astype(np.int64).sum()) * 256, **kern}
+        if algo == acbm.ALGO_ACBM:
+            out[name]["critical_frac"] = float((r["mode"] == acbm.MODE_CRITICAL).mean())
+    out["acbm"]["speedup_vs_fsbm"] = out["fsbm"]["ms"] / out["acbm"]["ms"]
+    return out
+
+
 def served_leg(acbm, synth, rates, seconds, nstreams=32, nfr=3):
     """Poisson arrivals of frame-pair FSBM requests over 32 streams whose
     resolution (640x480 .. 3840x2160) and p (16, 32, 64) are drawn per stream;
@@ -263,7 +305,7 @@ def main():
 
     do_f = args.only in (None, "fsbm")
     do_a = args.only in (None, "acbm")
-    if args.only in ("batch", "serve"):
+    if args.only in ("halfpel", "batch", "serve"):
         do_f = do_a = False
 
     def step(evs=None):
@@ -344,6 +386,8 @@ def main():
                                             if traffic else None),
                            "kernel": "k_search (FSBM window search, QSAD)",
                            "launch_ms": search_ms / search_n}
+    if args.only in (None, "halfpel"):
+        out["halfpel"] = halfpel_leg(torch, acbm, frames, prm, stream, args.steps)
     if args.only in (None, "batch") and not args.no_batch:
         out["batched"] = batched_leg(torch, acbm, synth, dev)
     if args.only in (None, "serve") and not args.no_serve:

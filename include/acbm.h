@@ -247,9 +247,9 @@ int acbm_autotune(const acbm_geom* g, uint32_t* best_rows, float* best_ms, void*
  * on the stream it runs on.  acbm_profile_read waits for the recorded events
  * and returns the summed device time and the launch count of one kernel
  * since the last reset.  Kernel names: "search" (window search, all block
- * sizes), "stats" (block statistics), "resolve" (FSBM argmin), "predictive"
- * (PBM/ACBM), "setup" (predictive workspace set-up), "field" (served field
- * extraction). */
+ * sizes), "stats" (block statistics), "half" (half-pel SADs around single
+ * possible winners), "resolve" (FSBM argmin), "predictive" (PBM/ACBM),
+ * "setup" (predictive workspace set-up), "field" (served field extraction). */
 int acbm_profile_enable(int on);
 int acbm_profile_reset(void);
 int acbm_profile_read(const char* kernel, double* total_ms, uint64_t* launches);

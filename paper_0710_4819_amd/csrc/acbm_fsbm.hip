@@ -414,8 +414,8 @@ __device__ __forceinline__ uint64_t wave_block_argmin(const BlockRec* __restrict
 // the half-pel predictor (px, py); the 8 half-pel positions around it are
 // priced with the same predictor and the cheapest of the nine is the block's
 // result, written straight to `out` (the rate needs the predictor, which is
-// known here).  A block with a single possible winner had its 8 SADs
-// prepared by k_half_prep; the others are computed here.
+// known here).  Used for blocks with several possible winners; the 8 SADs
+// are computed here from the frames.
 __device__ __forceinline__ void half_decide(const KGeom& g, const BlockRec* __restrict__ rec,
                                             const uint8_t* __restrict__ cur,
                                             const uint8_t* __restrict__ ref, int b, int px,
@@ -426,10 +426,7 @@ __device__ __forceinline__ void half_decide(const KGeom& g, const BlockRec* __re
   window_uv((uint32_t)(key & 0xFFFFu), 2 * p, &U0, &V0);
   const int r = b / g.bx, c = b - r * g.bx, x0 = c * g.bw, y0 = r * g.bh;
   uint32_t sads[8];
-  if (rec->count == 1) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) sads[k] = (rec->e[1 + k / 2] >> (16 * (k & 1))) & 0xFFFFu;
-  } else if (g.bw == 16 && g.bh == 16) {
+  if (g.bw == 16 && g.bh == 16) {
     wave_half_sads<16, 16>(g, cur, ref, x0, y0, U0, V0, sads);
   } else if (g.bw == 16) {
     wave_half_sads<16, 8>(g, cur, ref, x0, y0, U0, V0, sads);
@@ -469,10 +466,132 @@ __device__ __forceinline__ void half_decide(const KGeom& g, const BlockRec* __re
   }
 }
 
+// What the half-pel resolve needs of one block's record, loaded a step
+// ahead: the possible-winner count, the first entry and the 8 prepared
+// half-pel SADs (e[1..4]), and IntraX.
+struct HalfRec {
+  uint32_t count;
+  uint32_t e[5];
+  uint32_t intra_x;
+};
+
+// The same decision for a block with a single possible winner, by one lane
+// (its 8 half-pel SADs were prepared by k_half_prep).
+__device__ __forceinline__ void half_decide_lane(const KGeom& g, const HalfRec& h, int b, int px,
+                                                 int py, uint32_t lam,
+                                                 acbm_block_result* __restrict__ out,
+                                                 uint32_t* st) {
+  const int p = g.p;
+  const uint32_t* e = h.e;
+  int u = 0, v = 0;
+  window_uv(e[0] & 0xFFFFu, p, &u, &v);
+  const int U0 = 2 * u, V0 = 2 * v;
+  uint64_t best =
+      make_key((e[0] >> 16) + lam * (se_bits(U0 - px) + se_bits(V0 - py)), U0, V0, 2 * p);
+  uint32_t nh = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t sad = (e[1 + k / 2] >> (16 * (k & 1))) & 0xFFFFu;
+    if (sad == 0xFFFFu) continue;
+    int du, dv;
+    half_ring_offset(k, &du, &dv);
+    const int U = U0 + du, V = V0 + dv;
+    const uint64_t kk = make_key(sad + lam * (se_bits(U - px) + se_bits(V - py)), U, V, 2 * p);
+    best = kk < best ? kk : best;
+    ++nh;
+  }
+  int U = 0, V = 0;
+  window_uv((uint32_t)(best & 0xFFFFu), 2 * p, &U, &V);
+  const uint32_t rate = se_bits(U - px) + se_bits(V - py);
+  const uint32_t j = (uint32_t)(best >> 32), sad = j - lam * rate;
+  const int r = b / g.bx, c = b - r * g.bx;
+  acbm_block_result res;
+  res.mv.x = (int16_t)U;
+  res.mv.y = (int16_t)V;
+  res.sad = sad;
+  res.j = j;
+  res.rate_bits = rate;
+  res.cands = valid_count(p, c * g.bw, r * g.bh, g.bw, g.bh, g.width, g.height) + nh;
+  res.mode = ACBM_MODE_FSBM;
+  res.intra_x = h.intra_x;
+  *out = res;
+  *st = (sad << 16) | pack_mv(U, V);
+}
+
+// Half-pel resolve of one frame pair by the whole group.  Every block needs
+// its predictor (the half-pel step is priced with it), so the blocks are
+// decided in anti-diagonal order: step k holds the blocks (r, k - 2r), whose
+// left, top and top-right neighbours all belong to earlier steps.  The
+// blocks of a step are dealt round-robin over the waves (block i of the step
+// to wave i % nwaves, lane i / nwaves; a step has at most `by` blocks, which
+// the host keeps <= the group size); a block with a single possible winner
+// is decided by its own lane, the others by their whole wave.  Records do
+// not depend on any decision, so each thread loads its block of the next
+// step while the current step runs.
+__device__ __forceinline__ int step_block(const KGeom& g, int k, int i) {
+  const int r_lo = max(0, (k - (g.bx - 1) + 1) / 2), r_hi = min(g.by - 1, k / 2);
+  const int r = r_lo + i;
+  return r <= r_hi ? r * g.bx + (k - 2 * r) : -1;
+}
+
+__device__ __forceinline__ void load_half_rec(const BlockRec* __restrict__ recs, int b,
+                                              HalfRec& h) {
+  if (b < 0) return;
+  const BlockRec* rec = recs + b;
+  h.count = rec->count;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) h.e[q] = rec->e[q];
+  h.intra_x = rec->intra_x;
+}
+
+__device__ __forceinline__ void resolve_pair_half(const KGeom& g,
+                                                  const BlockRec* __restrict__ recs,
+                                                  const uint16_t* __restrict__ ovf,
+                                                  acbm_block_result* __restrict__ out,
+                                                  uint32_t lam, uint32_t* st,
+                                                  const uint8_t* __restrict__ cur,
+                                                  const uint8_t* __restrict__ ref) {
+  const int p = g.p, bx = g.bx, by = g.by;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int steps = (bx - 1) + 2 * (by - 1) + 1;
+  const int i = lane * nwaves + wave;  // this thread's place in every step
+  HalfRec h{}, hn{};
+  int b = step_block(g, 0, i);
+  load_half_rec(recs, b, h);
+  for (int k = 0; k < steps; ++k) {
+    const int bn = step_block(g, k + 1, i);
+    load_half_rec(recs, bn, hn);  // in flight while this step is decided
+    {
+      const int r = b >= 0 ? b / bx : 0, c = b >= 0 ? b - r * bx : 0;
+      int px = 0, py = 0;
+      bool multi = false;
+      if (b >= 0) {
+        median_pred(st, b, r, c, bx, &px, &py);  // its neighbours are decided
+        if (h.count == 1)
+          half_decide_lane(g, h, b, px, py, lam, out + b, st + b);
+        else
+          multi = true;
+      }
+      uint64_t mask = __ballot(multi);
+      while (mask) {
+        const int q = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const int bb = __shfl(b, q, 64);
+        const int qx = __shfl(px, q, 64), qy = __shfl(py, q, 64);
+        const uint64_t key =
+            wave_block_argmin<true>(recs + bb, ovf + (size_t)bb * ovf_stride(p), p, qx, qy, lam);
+        half_decide(g, recs + bb, cur, ref, bb, qx, qy, lam, key, out + bb, st + bb);
+      }
+    }
+    __syncthreads();  // this step's decisions before the next step reads them
+    b = bn;
+    h = hn;
+  }
+}
+
 // FSBM resolve of one frame pair by the whole group.  `st` is the pair's
 // decision state (LDS or workspace); `pending` a shared flag.  HP: half-pel
-// precision, vectors in half-pel units; cur and ref are then the pair's
-// frames (the half-pel step reads them).
+// precision (resolve_pair_half); cur and ref are then the pair's frames.
 template <bool HP>
 __device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __restrict__ recs,
                                              const uint16_t* __restrict__ ovf,
@@ -480,15 +599,18 @@ __device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __r
                                              uint32_t* st, int* pending_flag,
                                              const uint8_t* __restrict__ cur,
                                              const uint8_t* __restrict__ ref) {
+  if constexpr (HP) {
+    resolve_pair_half(g, recs, ovf, out, lam, st, cur, ref);
+    return;
+  }
   int& pending = *pending_flag;
   const int p = g.p, W = 2 * p + 1, nb = g.nb, bx = g.bx;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
 
   // blocks with a single possible winner are decided without a predictor
-  // (not with half-pel precision: their half-pel step needs it)
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
     uint32_t w = kOpen;
-    if (!HP && recs[b].count == 1) {
+    if (recs[b].count == 1) {
       const uint32_t e = recs[b].e[0];
       int u, v;
       window_uv(e & 0xFFFFu, p, &u, &v);
@@ -521,11 +643,7 @@ __device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __r
         const int bb = base + k;
         const int qx = __shfl(px, k, 64), qy = __shfl(py, k, 64);
         const uint64_t key =
-            wave_block_argmin<HP>(recs + bb, ovf + (size_t)bb * ovf_stride(p), p, qx, qy, lam);
-        if (HP) {
-          half_decide(g, recs + bb, cur, ref, bb, qx, qy, lam, key, out + bb, st + bb);
-          continue;
-        }
+            wave_block_argmin<false>(recs + bb, ovf + (size_t)bb * ovf_stride(p), p, qx, qy, lam);
         int u = 0, v = 0;
         uint32_t sad = 0;
         if (key != ~0ull) {
@@ -542,7 +660,6 @@ __device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __r
     __syncthreads();
     if (!again) break;
   }
-  if (HP) return;  // every result was written when its block was decided
 
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
     const int r = b / bx, c = b - r * bx;
