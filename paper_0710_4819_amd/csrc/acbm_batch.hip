@@ -247,11 +247,15 @@ int enqueue_batch(const acbm_job* jobs, size_t njobs, void* ws, hipStream_t st) 
       const acbm_job& jj = jobs[c.job_index[q]];
       char* sl = base + pl.slice[c.job_index[q]];
       BlockRec* recs = reinterpret_cast<BlockRec*>(sl + fsbm_recs_offset());
+      uint16_t* ovf = reinterpret_cast<uint16_t*>(sl + fsbm_ovf_offset(bj.g, bj.npairs));
+      const size_t ovf_per_pair = (size_t)bj.g.nb * fsbm_ovf_entries(bj.g.p);
       for (uint32_t p0 = 0; p0 < bj.npairs; p0 += kMaxPairsPerLaunch) {
         const int n = (int)std::min<uint32_t>(kMaxPairsPerLaunch, bj.npairs - p0);
         FramePtrs fr{};
         for (int k = 0; k <= n; ++k) fr.f[k] = jj.frames[p0 + k];
-        if ((rc = launch_half_prep(bj.g, fr, n, recs + (size_t)p0 * bj.g.nb, st))) return rc;
+        if ((rc = launch_half_prep(bj.g, fr, n, recs + (size_t)p0 * bj.g.nb,
+                                   ovf + p0 * ovf_per_pair, st)))
+          return rc;
       }
     }
     jo += c.jobs.size();

@@ -52,6 +52,7 @@ __device__ __forceinline__ uint64_t make_key(uint32_t j, int u, int v, int p) {
 extern "C" __device__ uint64_t __ockl_wfred_min_u64(uint64_t);
 extern "C" __device__ uint32_t __ockl_wfred_min_u32(uint32_t);
 extern "C" __device__ uint32_t __ockl_wfred_add_u32(uint32_t);
+extern "C" __device__ uint32_t __ockl_wfred_max_u32(uint32_t);
 namespace acbm {
 
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) { return __ockl_wfred_min_u64(x); }

@@ -38,6 +38,14 @@ __host__ __device__ __forceinline__ uint32_t ovf_list_cap(int p) {
   return (uint32_t)(ovf_stride(p) / 2);
 }
 
+// With half-pel precision, blocks with at most this many possible winners
+// get the 8 half-pel SADs around each winner prepared in their overflow
+// region (8 entries per winner), which they do not otherwise use.
+__host__ __device__ __forceinline__ uint32_t half_cap(int p) {
+  const uint32_t c = (uint32_t)(ovf_stride(p) / 8);
+  return c < (uint32_t)kShort ? c : (uint32_t)kShort;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs.  Remap so that each
 // XCD gets one contiguous band of blocks: neighbouring blocks share most of
 // their search windows, and a band then stays in one XCD's L2.
@@ -410,6 +418,47 @@ __device__ __forceinline__ uint64_t wave_block_argmin(const BlockRec* __restrict
   return wave_min_u64(best);
 }
 
+// The nine-way choice of the half-pel step: the integer winner (U0, V0) with
+// key `key`, and its 8 half-pel neighbours with SADs `sads` (0xFFFF: not a
+// valid candidate), all priced with the predictor (px, py).  `writer`
+// stores the block's result and its decision word.
+__device__ __forceinline__ void half_finish(const KGeom& g, int b, int U0, int V0, uint64_t key,
+                                            const uint32_t (&sads)[8], int px, int py,
+                                            uint32_t lam, uint32_t intra_x, bool writer,
+                                            acbm_block_result* __restrict__ out, uint32_t* st) {
+  const int p = g.p;
+  uint64_t best = key;
+  uint32_t nh = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (sads[k] == 0xFFFFu) continue;
+    int du, dv;
+    half_ring_offset(k, &du, &dv);
+    const int U = U0 + du, V = V0 + dv;
+    const uint64_t kk = make_key(sads[k] + lam * (se_bits(U - px) + se_bits(V - py)), U, V, 2 * p);
+    best = kk < best ? kk : best;
+    ++nh;
+  }
+  int U = 0, V = 0;
+  window_uv((uint32_t)(best & 0xFFFFu), 2 * p, &U, &V);
+  const uint32_t rate = se_bits(U - px) + se_bits(V - py);
+  const uint32_t j = (uint32_t)(best >> 32), sad = j - lam * rate;
+  if (writer) {
+    const int r = b / g.bx, c = b - r * g.bx;
+    acbm_block_result res;
+    res.mv.x = (int16_t)U;
+    res.mv.y = (int16_t)V;
+    res.sad = sad;
+    res.j = j;
+    res.rate_bits = rate;
+    res.cands = valid_count(p, c * g.bw, r * g.bh, g.bw, g.bh, g.width, g.height) + nh;
+    res.mode = ACBM_MODE_FSBM;
+    res.intra_x = intra_x;
+    *out = res;
+    *st = (sad << 16) | pack_mv(U, V);
+  }
+}
+
 // Half-pel step of block b (whole wave): `key` is the integer winner under
 // the half-pel predictor (px, py); the 8 half-pel positions around it are
 // priced with the same predictor and the cheapest of the nine is the block's
@@ -435,35 +484,40 @@ __device__ __forceinline__ void half_decide(const KGeom& g, const BlockRec* __re
   } else {
     wave_half_sads<8, 8>(g, cur, ref, x0, y0, U0, V0, sads);
   }
-  uint64_t best = key;
-  uint32_t nh = 0;
+  half_finish(g, b, U0, V0, key, sads, px, py, lam, rec->intra_x, lane == 0, out, st);
+}
+
+// Same, for a block whose winners' half-pel SADs were prepared in its
+// overflow region: lane s prices winner s and holds its 8 SADs.
+__device__ __forceinline__ void half_decide_prepared(const KGeom& g,
+                                                     const BlockRec* __restrict__ rec,
+                                                     const uint16_t* __restrict__ row,
+                                                     uint32_t count, int b, int px, int py,
+                                                     uint32_t lam,
+                                                     acbm_block_result* __restrict__ out,
+                                                     uint32_t* st) {
+  const int p = g.p, lane = threadIdx.x & 63;
+  uint64_t key = ~0ull;
+  uint4 hs = make_uint4(0u, 0u, 0u, 0u);
+  if (lane < (int)count) {
+    const uint32_t e = rec->e[lane];
+    hs = reinterpret_cast<const uint4*>(row)[lane];
+    int u = 0, v = 0;
+    window_uv(e & 0xFFFFu, p, &u, &v);
+    key = int_key<true>(e >> 16, u, v, p, px, py, lam);
+  }
+  const uint64_t k0 = wave_min_u64(key);
+  const int w = __builtin_ctzll(__ballot(key == k0));  // keys are unique
+  const uint32_t h4[4] = {(uint32_t)__builtin_amdgcn_readlane(hs.x, w),
+                          (uint32_t)__builtin_amdgcn_readlane(hs.y, w),
+                          (uint32_t)__builtin_amdgcn_readlane(hs.z, w),
+                          (uint32_t)__builtin_amdgcn_readlane(hs.w, w)};
+  uint32_t sads[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    if (sads[k] == 0xFFFFu) continue;
-    int du, dv;
-    half_ring_offset(k, &du, &dv);
-    const int U = U0 + du, V = V0 + dv;
-    const uint64_t kk = make_key(sads[k] + lam * (se_bits(U - px) + se_bits(V - py)), U, V, 2 * p);
-    best = kk < best ? kk : best;
-    ++nh;
-  }
-  int U = 0, V = 0;
-  window_uv((uint32_t)(best & 0xFFFFu), 2 * p, &U, &V);
-  const uint32_t rate = se_bits(U - px) + se_bits(V - py);
-  const uint32_t j = (uint32_t)(best >> 32), sad = j - lam * rate;
-  if (lane == 0) {
-    acbm_block_result res;
-    res.mv.x = (int16_t)U;
-    res.mv.y = (int16_t)V;
-    res.sad = sad;
-    res.j = j;
-    res.rate_bits = rate;
-    res.cands = valid_count(p, x0, y0, g.bw, g.bh, g.width, g.height) + nh;
-    res.mode = ACBM_MODE_FSBM;
-    res.intra_x = rec->intra_x;
-    *out = res;
-    *st = (sad << 16) | pack_mv(U, V);
-  }
+  for (int k = 0; k < 8; ++k) sads[k] = (h4[k / 2] >> (16 * (k & 1))) & 0xFFFFu;
+  int U0 = 0, V0 = 0;
+  window_uv((uint32_t)(k0 & 0xFFFFu), 2 * p, &U0, &V0);
+  half_finish(g, b, U0, V0, k0, sads, px, py, lam, rec->intra_x, lane == 0, out, st);
 }
 
 // What the half-pel resolve needs of one block's record, loaded a step
@@ -482,40 +536,13 @@ __device__ __forceinline__ void half_decide_lane(const KGeom& g, const HalfRec& 
                                                  acbm_block_result* __restrict__ out,
                                                  uint32_t* st) {
   const int p = g.p;
-  const uint32_t* e = h.e;
   int u = 0, v = 0;
-  window_uv(e[0] & 0xFFFFu, p, &u, &v);
-  const int U0 = 2 * u, V0 = 2 * v;
-  uint64_t best =
-      make_key((e[0] >> 16) + lam * (se_bits(U0 - px) + se_bits(V0 - py)), U0, V0, 2 * p);
-  uint32_t nh = 0;
+  window_uv(h.e[0] & 0xFFFFu, p, &u, &v);
+  const uint64_t key = int_key<true>(h.e[0] >> 16, u, v, p, px, py, lam);
+  uint32_t sads[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const uint32_t sad = (e[1 + k / 2] >> (16 * (k & 1))) & 0xFFFFu;
-    if (sad == 0xFFFFu) continue;
-    int du, dv;
-    half_ring_offset(k, &du, &dv);
-    const int U = U0 + du, V = V0 + dv;
-    const uint64_t kk = make_key(sad + lam * (se_bits(U - px) + se_bits(V - py)), U, V, 2 * p);
-    best = kk < best ? kk : best;
-    ++nh;
-  }
-  int U = 0, V = 0;
-  window_uv((uint32_t)(best & 0xFFFFu), 2 * p, &U, &V);
-  const uint32_t rate = se_bits(U - px) + se_bits(V - py);
-  const uint32_t j = (uint32_t)(best >> 32), sad = j - lam * rate;
-  const int r = b / g.bx, c = b - r * g.bx;
-  acbm_block_result res;
-  res.mv.x = (int16_t)U;
-  res.mv.y = (int16_t)V;
-  res.sad = sad;
-  res.j = j;
-  res.rate_bits = rate;
-  res.cands = valid_count(p, c * g.bw, r * g.bh, g.bw, g.bh, g.width, g.height) + nh;
-  res.mode = ACBM_MODE_FSBM;
-  res.intra_x = h.intra_x;
-  *out = res;
-  *st = (sad << 16) | pack_mv(U, V);
+  for (int k = 0; k < 8; ++k) sads[k] = (h.e[1 + k / 2] >> (16 * (k & 1))) & 0xFFFFu;
+  half_finish(g, b, 2 * u, 2 * v, key, sads, px, py, lam, h.intra_x, true, out, st);
 }
 
 // Half-pel resolve of one frame pair by the whole group.  Every block needs
@@ -578,9 +605,14 @@ __device__ __forceinline__ void resolve_pair_half(const KGeom& g,
         mask &= mask - 1;
         const int bb = __shfl(b, q, 64);
         const int qx = __shfl(px, q, 64), qy = __shfl(py, q, 64);
-        const uint64_t key =
-            wave_block_argmin<true>(recs + bb, ovf + (size_t)bb * ovf_stride(p), p, qx, qy, lam);
-        half_decide(g, recs + bb, cur, ref, bb, qx, qy, lam, key, out + bb, st + bb);
+        const uint32_t cnt = (uint32_t)__shfl((int)h.count, q, 64);
+        const uint16_t* row = ovf + (size_t)bb * ovf_stride(p);
+        if (cnt <= half_cap(p)) {
+          half_decide_prepared(g, recs + bb, row, cnt, bb, qx, qy, lam, out + bb, st + bb);
+        } else {
+          const uint64_t key = wave_block_argmin<true>(recs + bb, row, p, qx, qy, lam);
+          half_decide(g, recs + bb, cur, ref, bb, qx, qy, lam, key, out + bb, st + bb);
+        }
       }
     }
     __syncthreads();  // this step's decisions before the next step reads them
@@ -604,7 +636,7 @@ __device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __r
     return;
   }
   int& pending = *pending_flag;
-  const int p = g.p, W = 2 * p + 1, nb = g.nb, bx = g.bx;
+  const int p = g.p, nb = g.nb, bx = g.bx;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
 
   // blocks with a single possible winner are decided without a predictor
@@ -699,29 +731,94 @@ k_resolve(const KGeom g, const BlockRec* __restrict__ recs, const uint16_t* __re
                    HP ? fr.f[pair + 1] : nullptr, HP ? fr.f[pair] : nullptr);
 }
 
-// Half-pel SADs around the single possible winner of every block that has
-// one (the 92 % or so of blocks the resolve could otherwise decide without
-// a predictor): one wave per (pair, block), written to the free slots
-// e[1..4] of its record (8 u16, ring order).  These do not depend on the
-// predictor, so they are computed here, in parallel, off the resolve's
-// sequential path.
+// Half-pel SADs prepared off the resolve's sequential path.  For every block
+// with at most half_cap(p) possible winners, the 8 half-pel neighbours of
+// each winner (they do not depend on the predictor): a single winner's go to
+// the free record slots e[1..4], several winners' to the block's overflow
+// region (winner s at entries 8s .. 8s+7), which only blocks with more than
+// kShort winners use otherwise.  Ring order as half_ring_offset.
+// One lane per block row: 64 / M blocks per wave.  A lane loads, for one
+// winner (u, v), reference rows y0+j+v-1 .. y0+j+v+1 over the bytes
+// x0+u-1 .. x0+u+N (two dword-aligned windows, for the left and the other
+// columns) and its current row once, and computes its row of all 8
+// neighbours from registers; the M rows of a neighbour are summed by DPP.
+// Loads of invalid neighbours are clamped into the frame and their sums
+// dropped.
 template <int N, int M>
 __global__ void __launch_bounds__(256)
-k_half_prep(const KGeom g, const FramePtrs fr, int npairs, BlockRec* __restrict__ recs) {
-  const int lane = threadIdx.x & 63;
-  const size_t item = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (item >= (size_t)npairs * g.nb) return;
-  const int pair = (int)(item / (size_t)g.nb), b = (int)(item % (size_t)g.nb);
-  BlockRec* rec = recs + item;
-  if (rec->count != 1) return;  // the same word for the whole wave
-  int u = 0, v = 0;
-  window_uv(rec->e[0] & 0xFFFFu, g.p, &u, &v);
+k_half_prep(const KGeom g, const FramePtrs fr, int npairs, BlockRec* __restrict__ recs,
+            uint16_t* __restrict__ ovf) {
+  constexpr int NC = N / 4, PER = 64 / M;
+  const int lane = threadIdx.x & 63, j = lane % M;
+  const size_t item = ((size_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * PER + lane / M;
+  const size_t items = (size_t)npairs * g.nb;
+  const int p = g.p;
+  const uint32_t cap = half_cap(p);
+  int pair = 0, b = 0;
+  uint32_t count = 0;
+  if (item < items) {
+    pair = (int)(item / (size_t)g.nb);
+    b = (int)(item % (size_t)g.nb);
+    count = recs[item].count;
+  }
+  const uint32_t ns = (count >= 1 && count <= cap) ? count : 0u;  // winners to prepare
+  const uint32_t smax = __builtin_amdgcn_readfirstlane(__ockl_wfred_max_u32(ns));
   const int r = b / g.bx, c = b - r * g.bx;
-  uint32_t sads[8];
-  wave_half_sads<N, M>(g, fr.f[pair + 1], fr.f[pair], c * N, r * M, 2 * u, 2 * v, sads);
-  if (lane == 0) {
+  const int x0 = c * N, y0 = r * M;
+  const uint8_t* __restrict__ cur = fr.f[pair + 1];
+  const uint8_t* __restrict__ ref = fr.f[pair];
+  const int last_dw = (g.pitch >> 2) - 1;
+  uint32_t cw[NC];
+  if (ns) {
+    const uint32_t* cr = reinterpret_cast<const uint32_t*>(cur + (size_t)(y0 + j) * g.pitch + x0);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) rec->e[1 + q] = sads[2 * q] | (sads[2 * q + 1] << 16);
+    for (int q = 0; q < NC; ++q) cw[q] = cr[q];
+  }
+  for (uint32_t s = 0; s < smax; ++s) {
+    const bool act = s < ns;
+    int u = 0, v = 0;
+    if (act) window_uv(recs[item].e[s] & 0xFFFFu, p, &u, &v);
+    // rows v-1, v, v+1 and the two column windows, clamped into the frame
+    uint32_t wa[3][NC + 1], wb[3][NC + 1];
+    const int xa = x0 + u - 1, xb = x0 + u;
+    const int da = max(xa, 0) >> 2, db = xb >> 2;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int y = min(max(y0 + j + v - 1 + t, 0), g.height - 1);
+      const uint32_t* row = reinterpret_cast<const uint32_t*>(ref + (size_t)y * g.pitch);
+#pragma unroll
+      for (int q = 0; q <= NC; ++q) {
+        wa[t][q] = act ? row[min(da + q, last_dw)] : 0u;
+        wb[t][q] = act ? row[min(max(db, 0) + q, last_dw)] : 0u;
+      }
+    }
+    const uint32_t sha = (uint32_t)(xa & 3), shb = (uint32_t)(xb & 3);
+    uint32_t sums[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      int du, dv;
+      half_ring_offset(k, &du, &dv);
+      const int U = 2 * u + du, V = 2 * v + dv;
+      const bool ok = act && cand_valid_half(U, V, p, x0, y0, N, M, g.width, g.height);
+      // rows: dv = -1 reads v-1 and v; dv = 0 reads v; dv = +1 reads v and v+1
+      const int t0 = dv < 0 ? 0 : 1, t1 = dv > 0 ? 2 : 1;
+      const uint32_t(&w0)[NC + 1] = du < 0 ? wa[t0] : wb[t0];
+      const uint32_t(&w1)[NC + 1] = du < 0 ? wa[t1] : wb[t1];
+      const uint32_t acc = ok ? half_row_sad<NC>(w0, w1, du < 0 ? sha : shb, U & 1, V & 1, cw, 0u)
+                              : 0u;
+      const uint32_t sum = group_sum<M>(acc);
+      sums[k] = ok ? sum : 0xFFFFu;
+    }
+    if (act && j == 0) {
+      if (count == 1) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) recs[item].e[1 + q] = sums[2 * q] | (sums[2 * q + 1] << 16);
+      } else {
+        uint4* dst = reinterpret_cast<uint4*>(ovf + item * ovf_stride(p)) + s;
+        *dst = make_uint4(sums[0] | (sums[1] << 16), sums[2] | (sums[3] << 16),
+                          sums[4] | (sums[5] << 16), sums[6] | (sums[7] << 16));
+      }
+    }
   }
 }
 
@@ -918,6 +1015,8 @@ static size_t ovf_row_bytes(const KGeom& g) { return ovf_stride(g.p) * sizeof(ui
 constexpr size_t kResolveLdsMax = 144 * 1024;
 
 size_t fsbm_recs_offset() { return align256(sizeof(WsHeader)); }
+size_t fsbm_ovf_entries(int p) { return ovf_stride(p); }
+
 size_t fsbm_ovf_offset(const KGeom& g, uint32_t npairs) {
   return fsbm_recs_offset() + align256((size_t)npairs * g.nb * sizeof(BlockRec));
 }
@@ -945,18 +1044,19 @@ uint32_t fsbm_slack(int p, const acbm_params& prm) {
 }
 
 int launch_half_prep(const KGeom& g, const FramePtrs& fr, int npairs, BlockRec* recs,
-                     hipStream_t st) {
+                     uint16_t* ovf, hipStream_t st) {
   const size_t items = (size_t)npairs * g.nb;
-  const dim3 grid((unsigned)((items + 3) / 4)), block(256);
+  const size_t per_group = 4 * (64 / (size_t)g.bh);  // 4 waves, 64 / M blocks per wave
+  const dim3 grid((unsigned)((items + per_group - 1) / per_group)), block(256);
   ProfScope ps("half", st);
   if (g.bw == 16 && g.bh == 16)
-    hipLaunchKernelGGL((k_half_prep<16, 16>), grid, block, 0, st, g, fr, npairs, recs);
+    hipLaunchKernelGGL((k_half_prep<16, 16>), grid, block, 0, st, g, fr, npairs, recs, ovf);
   else if (g.bw == 16 && g.bh == 8)
-    hipLaunchKernelGGL((k_half_prep<16, 8>), grid, block, 0, st, g, fr, npairs, recs);
+    hipLaunchKernelGGL((k_half_prep<16, 8>), grid, block, 0, st, g, fr, npairs, recs, ovf);
   else if (g.bw == 8 && g.bh == 16)
-    hipLaunchKernelGGL((k_half_prep<8, 16>), grid, block, 0, st, g, fr, npairs, recs);
+    hipLaunchKernelGGL((k_half_prep<8, 16>), grid, block, 0, st, g, fr, npairs, recs, ovf);
   else if (g.bw == 8 && g.bh == 8)
-    hipLaunchKernelGGL((k_half_prep<8, 8>), grid, block, 0, st, g, fr, npairs, recs);
+    hipLaunchKernelGGL((k_half_prep<8, 8>), grid, block, 0, st, g, fr, npairs, recs, ovf);
   else
     return fail(ACBM_E_UNSUPPORTED, "block size must be 8 or 16 in each direction");
   hipError_t e = hipGetLastError();
@@ -987,7 +1087,7 @@ int launch_fsbm(const KGeom& g, const acbm_params& prm, const uint8_t* const* fr
     uint16_t* o = ovf + (size_t)p0 * g.nb * (ovf_row_bytes(g) / 2);
     int rc = launch_search<false>(g, fr, n, nullptr, r, o, slack, st);
     if (rc) return rc;
-    if (hp && (rc = launch_half_prep(g, fr, n, r, st))) return rc;
+    if (hp && (rc = launch_half_prep(g, fr, n, r, o, st))) return rc;
     const size_t rlds = mv_in_lds ? (size_t)g.nb * sizeof(uint32_t) : 0;
     const void* fn = hp ? (const void*)k_resolve<true> : (const void*)k_resolve<false>;
     if (rlds > 64 * 1024)

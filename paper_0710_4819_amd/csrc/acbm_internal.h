@@ -133,15 +133,17 @@ int launch_fsbm(const KGeom& g, const acbm_params& prm, const uint8_t* const* fr
                 hipStream_t s);
 // Window search with an explicit plan, over `npairs` pairs of one job
 // (kTable = false: BlockRec + overflow rows).
-// Half-pel SADs around the single possible winner of the blocks that have
-// one (records of `npairs` pairs), before a half-pel resolve.
+// Half-pel SADs around the possible winners of the blocks that have few
+// (records and overflow regions of `npairs` pairs), before a half-pel
+// resolve.
 int launch_half_prep(const KGeom& g, const FramePtrs& fr, int npairs, BlockRec* recs,
-                     hipStream_t st);
+                     uint16_t* ovf, hipStream_t st);
 int launch_search_plan(const KGeom& g, const SearchPlan& pl, const uint8_t* const* frames,
                        int npairs, BlockRec* recs, uint16_t* ovf, uint32_t slack,
                        hipStream_t s);
 size_t fsbm_recs_offset();                    // BlockRec array offset in an FSBM workspace
 size_t fsbm_ovf_offset(const KGeom& g, uint32_t npairs);
+size_t fsbm_ovf_entries(int p);  // u16 entries of one block's overflow region
 size_t fsbm_mv_offset(const KGeom& g, uint32_t npairs);  // resolve state, if used
 bool fsbm_mv_in_lds(const KGeom& g);
 // Batch kernels: the full search of one group (at most 64 jobs with the
