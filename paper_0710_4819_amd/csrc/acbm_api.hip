@@ -162,6 +162,7 @@ static SearchPlan plan_for(int N, int M, int p, int R, int max_threads, double* 
     rounds = (tasks + threads - 1) / threads;
   }
   if (lds > lds_limit()) return SearchPlan{0, 0, 0};
+  if (threads < s.dws) return SearchPlan{0, 0, 0};  // the window load gives each dword column a thread
   const double valu = (double)R * M * (N / 4) * qsad_cost();
   const double ldsc = (double)(R + M - 1) * N;
   // kWaveFixed: per-wave cost of the window load, the scalar load of the

@@ -91,6 +91,19 @@ __device__ __forceinline__ ValidBox valid_box(int p, int x0, int y0, int N, int 
 // Sets the 16-bit lane of every invalid candidate of a task to 0xFFFF (no
 // valid SAD reaches it: 255 * 256 = 65280).  Lane i of acc[rr] is candidate
 // (u0 + i, v0 + rr).
+// For a block whose whole window is valid only the padding is invalid: the
+// columns of the first and last quads outside [-p, p] (u_lo = -4*ceil(p/4)
+// may lie below -p) and the last row group's rows beyond +p.
+template <int R>
+__device__ __forceinline__ void mask_padding(uint64_t (&acc)[R], int p, int u0, int v0) {
+  uint64_t colmask = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (u0 + i < -p || u0 + i > p) colmask |= 0xFFFFull << (16 * i);
+#pragma unroll
+  for (int rr = 0; rr < R; ++rr) acc[rr] |= (v0 + rr > p) ? ~0ull : colmask;
+}
+
 template <int R>
 __device__ __forceinline__ void mask_invalid(uint64_t (&acc)[R], const ValidBox& bx, int u0,
                                              int v0) {
@@ -103,6 +116,19 @@ __device__ __forceinline__ void mask_invalid(uint64_t (&acc)[R], const ValidBox&
     const int v = v0 + rr;
     acc[rr] |= (v < bx.v_min || v > bx.v_max) ? ~0ull : colmask;
   }
+}
+
+// Workgroup minimum of a 32-bit value (`scratch`: one slot per wave).
+__device__ __forceinline__ uint32_t group_min_u32(uint32_t x, uint32_t* scratch) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  x = wave_min_u32(x);
+  if (lane == 0) scratch[wave] = x;
+  __syncthreads();
+  uint32_t m = scratch[0];
+  for (int w = 1; w < nw; ++w) m = scratch[w] < m ? scratch[w] : m;
+  __syncthreads();
+  return m;
 }
 
 // Workgroup minimum; `scratch` holds one slot per wave.  Every thread gets
@@ -140,48 +166,48 @@ __host__ __device__ inline WindowShape window_shape(int p, int R) {
   s.rows = s.groups * R + M - 1;
   s.dws = s.quads + N / 4;
   s.stride = s.dws | 1;  // odd stride spreads row starts over the LDS banks
+  s.qmagic = (uint32_t)(((1ull << 32) + (uint64_t)s.quads - 1) / (uint64_t)s.quads);
+  s.dmagic = (uint32_t)(((1ull << 32) + (uint64_t)s.dws - 1) / (uint64_t)s.dws);
   return s;
 }
 
-// Cooperative load of the window into LDS (all threads of the group).  Each
-// thread walks (row, dword) positions blockDim.x apart with a carry instead
-// of dividing per element; a window that lies inside the frame (the common
-// case, decided once per block) skips the per-dword bounds test.
+// Cooperative load of the window into LDS (all threads of the group).  The
+// group covers `per` = blockDim / dws whole rows at a time: each thread owns
+// one dword column and walks down it `per` rows per step, so the addresses
+// advance by constants; the threads beyond per * dws (fewer than dws) cover
+// the rows left over.  A window inside the frame (the common case, decided
+// once per block) skips the per-dword bounds test.
 template <int N, int M>
 __device__ inline void load_window(uint32_t* __restrict__ win, const WindowShape& s,
                                    const uint8_t* __restrict__ ref, int pitch, int width,
                                    int height, int x0, int y0) {
   const int xs = x0 + s.u_lo;  // multiple of 4
   const int ys = y0 - s.p;
-  const int nt = (int)blockDim.x;
-  const int drow = nt / s.dws, ddw = nt - drow * s.dws;
-  int row = (int)threadIdx.x / s.dws;
-  int dw = (int)threadIdx.x - row * s.dws;
+  const int per = (int)blockDim.x / s.dws;  // >= 1: the plan gives every row a thread
+  const int r0 = (int)__umulhi(threadIdx.x, s.dmagic);
+  const int dw = (int)threadIdx.x - r0 * s.dws;
+  const int main_rows = s.rows - s.rows % per;  // rows covered in whole steps
   const bool inside = xs >= 0 && xs + 4 * s.dws <= width && ys >= 0 && ys + s.rows <= height;
   if (inside) {
-    const uint8_t* base = ref + (size_t)ys * pitch + xs;
-    while (row < s.rows) {
-      win[row * s.stride + dw] = *reinterpret_cast<const uint32_t*>(base + (size_t)row * pitch + 4 * dw);
-      row += drow;
-      dw += ddw;
-      if (dw >= s.dws) {
-        dw -= s.dws;
-        ++row;
-      }
+    const uint8_t* base = ref + (size_t)ys * pitch + xs + 4 * dw;
+    if (r0 < per) {
+#pragma unroll 4
+      for (int row = r0; row < main_rows; row += per)
+        win[row * s.stride + dw] = *reinterpret_cast<const uint32_t*>(base + (size_t)row * pitch);
     }
+    // the last rows % per rows: one per group of dws threads
+    const int row = main_rows + r0;
+    if (r0 < per && row < s.rows)
+      win[row * s.stride + dw] = *reinterpret_cast<const uint32_t*>(base + (size_t)row * pitch);
   } else {
-    while (row < s.rows) {
-      const int y = ys + row, x = xs + 4 * dw;
+    const int x = xs + 4 * dw;
+    const bool xok = x >= 0 && x + 3 < width;
+    for (int row = r0; r0 < per && row < s.rows; row += per) {
+      const int y = ys + row;
       uint32_t val = 0;
-      if (y >= 0 && y < height && x >= 0 && x + 3 < width)
+      if (xok && y >= 0 && y < height)
         val = *reinterpret_cast<const uint32_t*>(ref + (size_t)y * pitch + x);
       win[row * s.stride + dw] = val;
-      row += drow;
-      dw += ddw;
-      if (dw >= s.dws) {
-        dw -= s.dws;
-        ++row;
-      }
     }
   }
 }

@@ -118,8 +118,8 @@ __device__ __forceinline__ void search_block(const KGeom& g, const WindowShape& 
   const int tasks = s.quads * s.groups;
   const int t = threadIdx.x;
   const bool active = t < tasks;
-  const int q = active ? t % s.quads : 0;
-  const int gi = active ? t / s.quads : 0;
+  const int gi = active ? (int)__umulhi((uint32_t)t, s.qmagic) : 0;  // t / quads
+  const int q = active ? t - gi * s.quads : 0;
   uint64_t acc[R];
   if (active) task_sads<N, M, R>(win, s.stride, q, gi, cb, acc);
 
@@ -127,14 +127,20 @@ __device__ __forceinline__ void search_block(const KGeom& g, const WindowShape& 
   // invalid candidates (outside the frame, or the padding of the quads and
   // row groups beyond +-p) read as 0xFFFF from here on
   const ValidBox vbox = valid_box(p, x0, y0, N, M, g.width, g.height);
-  if (active) mask_invalid<R>(acc, vbox, u0, v0);
+  const bool whole = vbox.u_min == -p && vbox.u_max == p && vbox.v_min == -p && vbox.v_max == p;
+  if (active) {
+    if (whole)
+      mask_padding<R>(acc, p, u0, v0);
+    else
+      mask_invalid<R>(acc, vbox, u0, v0);
+  }
 
   if (K == kKindStats) {
     // SAD_deviation = sum over the valid window of SAD - SAD_min.  Per lane
     // at most 4*R*65280 < 2^32; per wave at most 64 times that < 2^32 for
     // R <= 16, so u32 sums are exact and the group total is summed in u64.
     const uint32_t lmin = active ? min_u16_lanes<R>(acc) : 0xFFFFu;
-    const uint32_t smin = (uint32_t)group_min_u64(lmin, red);
+    const uint32_t smin = group_min_u32(lmin, reinterpret_cast<uint32_t*>(red));
     uint32_t dev = 0, nvalid = 0;
     if (active) {
 #pragma unroll
@@ -187,7 +193,7 @@ __device__ __forceinline__ void search_block(const KGeom& g, const WindowShape& 
 
   // ---- FSBM: SAD minimum and the candidates that can still win ----------
   const uint32_t lmin = active ? min_u16_lanes<R>(acc) : 0xFFFFu;
-  const uint32_t smin = (uint32_t)group_min_u64(lmin, red);
+  const uint32_t smin = group_min_u32(lmin, reinterpret_cast<uint32_t*>(red));
   const uint32_t thr = (uint32_t)min<uint64_t>((uint64_t)smin + slack, 0xFFFEu);
 
   if (active && lmin <= thr) {  // rare: this lane holds a possible winner

@@ -48,6 +48,9 @@ struct WindowShape {
   int rows;    // LDS rows (>= groups*R + M - 1)
   int dws;     // dwords per LDS row (>= quads + N/4)
   int stride;  // LDS row stride in dwords
+  // ceil(2^32 / quads) and ceil(2^32 / dws): t / d == umulhi(t, magic)
+  // exactly for every t < 2^16 and d < 2^8 (checked exhaustively)
+  uint32_t qmagic, dmagic;
 };
 
 // One FSBM job of a batch as the batch kernels read it (device memory).
