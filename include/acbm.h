@@ -29,7 +29,8 @@
  *    stream: argument errors return synchronously before anything is
  *    enqueued; device failures surface on a later call or synchronisation.
  *  - GPU layout requirements: frame pointers and pitch 4-byte aligned,
- *    block_w and block_h in {8, 16}, p <= 127.  Other shapes the method allows
+ *    block_w and block_h in {8, 16}, p <= 127, and for the searches at most
+ *    1024 block rows (height / block_h).  Other shapes the method allows
  *    return ACBM_E_UNSUPPORTED.
  */
 #ifndef ACBM_H

@@ -71,8 +71,8 @@ int check_params(const acbm_params* prm, const KGeom& k) {
   if (prm->subpel > 1) return fail(ACBM_E_INVAL, "subpel must be 0 or 1");
   if (prm->subpel && k.p > 63)
     return fail(ACBM_E_RANGE, "half-pel vectors need p <= 63");
-  if (prm->subpel && k.by > 1024)  // the half-pel resolve gives each block row one thread
-    return fail(ACBM_E_UNSUPPORTED, "half-pel precision needs at most 1024 block rows");
+  if (k.by > 1024)  // the FSBM resolve gives each block row of a step one thread
+    return fail(ACBM_E_UNSUPPORTED, "at most 1024 block rows");
   const uint64_t jmax =
       255ull * k.bw * k.bh + (uint64_t)prm->lambda * rate_max(prm->subpel ? 2 * k.p : k.p);
   if (jmax >= (1ull << 32)) return fail(ACBM_E_RANGE, "lambda too large: J would not fit 32 bits");

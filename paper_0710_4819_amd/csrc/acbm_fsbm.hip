@@ -315,7 +315,6 @@ __device__ __forceinline__ void window_uv(uint32_t ras, int p, int* u, int* v) {
 
 // Per-block state of the resolve: the decided vector packed in the low 16
 // bits (kMvUnset while open) and its SAD in the high 16 bits.
-constexpr uint32_t kOpen = 0xFFFF0000u | kMvUnset;
 __device__ __forceinline__ bool is_open(uint32_t w) { return (w & 0xFFFFu) == kMvUnset; }
 
 // Predictor of block b from the decided vectors; false if one of the three
@@ -627,25 +626,141 @@ __device__ __forceinline__ void resolve_pair_half(const KGeom& g,
   }
 }
 
-// FSBM resolve of one frame pair by the whole group.  `st` is the pair's
-// decision state (LDS or workspace); `pending` a shared flag.  HP: half-pel
-// precision (resolve_pair_half); cur and ref are then the pair's frames.
-template <bool HP>
-__device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __restrict__ recs,
-                                             const uint16_t* __restrict__ ovf,
-                                             acbm_block_result* __restrict__ out, uint32_t lam,
-                                             uint32_t* st, int* pending_flag,
-                                             const uint8_t* __restrict__ cur,
-                                             const uint8_t* __restrict__ ref) {
-  if constexpr (HP) {
-    resolve_pair_half(g, recs, ovf, out, lam, st, cur, ref);
-    return;
+// Integer resolve: the same anti-diagonal order as the half-pel one.  Each
+// thread prefetches the whole record of its block of the next step (header
+// and the kShort listed winners, 8 x 16 bytes), so that a block with at most
+// kShort possible winners is priced by its own lane with no memory access
+// on the sequential path; a block with more (list or row formats) is priced
+// by its whole wave.
+struct IntRec {
+  uint4 h;      // sad_min, count, intra_x, pad
+  uint4 e[7];   // the kShort = 28 listed winners
+};
+static_assert(kShort == 28, "the record's list is 7 x 16 bytes");
+
+__device__ __forceinline__ void load_int_rec(const BlockRec* __restrict__ recs, int b,
+                                             IntRec& r) {
+  if (b < 0) return;
+  const uint4* q = reinterpret_cast<const uint4*>(recs + b);
+  r.h = q[0];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) r.e[k] = q[1 + k];
+}
+
+// The decided block's result and decision word.
+__device__ __forceinline__ void int_write(const KGeom& g, int b, int u, int v, uint32_t sad,
+                                          int px, int py, uint32_t lam, uint32_t intra_x,
+                                          acbm_block_result* __restrict__ out, uint32_t* st) {
+  const int r = b / g.bx, c = b - r * g.bx;
+  const uint32_t rate = se_bits(u - px) + se_bits(v - py);
+  acbm_block_result res;
+  res.mv.x = (int16_t)u;
+  res.mv.y = (int16_t)v;
+  res.sad = sad;
+  res.j = sad + lam * rate;
+  res.rate_bits = rate;
+  res.cands = valid_count(g.p, c * g.bw, r * g.bh, g.bw, g.bh, g.width, g.height);
+  res.mode = ACBM_MODE_FSBM;
+  res.intra_x = intra_x;
+  *out = res;
+  *st = (sad << 16) | pack_mv(u, v);
+}
+
+__device__ __forceinline__ void int_decide_lane(const KGeom& g, const IntRec& rec, int b, int px,
+                                                int py, uint32_t lam,
+                                                acbm_block_result* __restrict__ out,
+                                                uint32_t* st) {
+  const int p = g.p;
+  const uint32_t W = 2u * (uint32_t)p + 1u;
+  const uint32_t inv = (uint32_t)(((1ull << 32) + W - 1) / W);  // ras / W = umulhi(ras, inv)
+  const uint32_t count = rec.h.y;
+  const uint32_t e[kShort] = {rec.e[0].x, rec.e[0].y, rec.e[0].z, rec.e[0].w, rec.e[1].x,
+                              rec.e[1].y, rec.e[1].z, rec.e[1].w, rec.e[2].x, rec.e[2].y,
+                              rec.e[2].z, rec.e[2].w, rec.e[3].x, rec.e[3].y, rec.e[3].z,
+                              rec.e[3].w, rec.e[4].x, rec.e[4].y, rec.e[4].z, rec.e[4].w,
+                              rec.e[5].x, rec.e[5].y, rec.e[5].z, rec.e[5].w, rec.e[6].x,
+                              rec.e[6].y, rec.e[6].z, rec.e[6].w};
+  uint64_t best = ~0ull;
+#pragma unroll
+  for (int s = 0; s < kShort; ++s) {
+    if (s >= (int)count) break;
+    const uint32_t ras = e[s] & 0xFFFFu;
+    const uint32_t vq = __umulhi(ras, inv);
+    const int v = (int)vq - p, u = (int)(ras - vq * W) - p;
+    const uint64_t k = int_key<false>(e[s] >> 16, u, v, p, px, py, lam);
+    best = k < best ? k : best;
   }
+  const uint32_t ras = (uint32_t)(best & 0xFFFFu);
+  const uint32_t vq = __umulhi(ras, inv);
+  const int v = (int)vq - p, u = (int)(ras - vq * W) - p;
+  const uint32_t sad = (uint32_t)(best >> 32) - lam * (se_bits(u - px) + se_bits(v - py));
+  int_write(g, b, u, v, sad, px, py, lam, rec.h.z, out, st);
+}
+
+__device__ __forceinline__ void resolve_pair_int(const KGeom& g,
+                                                 const BlockRec* __restrict__ recs,
+                                                 const uint16_t* __restrict__ ovf,
+                                                 acbm_block_result* __restrict__ out,
+                                                 uint32_t lam, uint32_t* st) {
+  const int p = g.p, bx = g.bx, by = g.by;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int steps = (bx - 1) + 2 * (by - 1) + 1;
+  const int i = lane * nwaves + wave;  // this thread's place in every step
+  IntRec h{}, hn{};
+  int b = step_block(g, 0, i);
+  load_int_rec(recs, b, h);
+  for (int k = 0; k < steps; ++k) {
+    const int bn = step_block(g, k + 1, i);
+    load_int_rec(recs, bn, hn);  // in flight while this step is decided
+    {
+      const int r = b >= 0 ? b / bx : 0, c = b >= 0 ? b - r * bx : 0;
+      int px = 0, py = 0;
+      bool multi = false;
+      if (b >= 0) {
+        median_pred(st, b, r, c, bx, &px, &py);  // its neighbours are decided
+        if (h.h.y <= (uint32_t)kShort)
+          int_decide_lane(g, h, b, px, py, lam, out + b, st + b);
+        else
+          multi = true;
+      }
+      uint64_t mask = __ballot(multi);
+      while (mask) {
+        const int q = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const int bb = __shfl(b, q, 64);
+        const int qx = __shfl(px, q, 64), qy = __shfl(py, q, 64);
+        const uint32_t ix = (uint32_t)__shfl((int)h.h.z, q, 64);
+        const uint64_t key =
+            wave_block_argmin<false>(recs + bb, ovf + (size_t)bb * ovf_stride(p), p, qx, qy, lam);
+        int u = 0, v = 0;
+        window_uv((uint32_t)(key & 0xFFFFu), p, &u, &v);
+        const uint32_t sad = (uint32_t)(key >> 32) - lam * (se_bits(u - qx) + se_bits(v - qy));
+        if (lane == 0) int_write(g, bb, u, v, sad, qx, qy, lam, ix, out + bb, st + bb);
+      }
+    }
+    __syncthreads();  // this step's decisions before the next step reads them
+    b = bn;
+    h = hn;
+  }
+}
+
+// Integer resolve when few blocks have several possible winners: blocks
+// with a single one are decided at once, in parallel, without a predictor;
+// the rest are decided in sweeps as soon as their left, top and top-right
+// neighbours are (each sweep decides at least the first open block in
+// raster order, so nb sweeps always suffice); a wave prices each ready block
+// of its 64-block chunk together.  Results are written in a final parallel
+// pass.
+constexpr uint32_t kOpen = 0xFFFF0000u | kMvUnset;
+
+__device__ __forceinline__ void resolve_pair_sweeps(const KGeom& g,
+                                                    const BlockRec* __restrict__ recs,
+                                                    const uint16_t* __restrict__ ovf,
+                                                    acbm_block_result* __restrict__ out,
+                                                    uint32_t lam, uint32_t* st, int* pending_flag) {
   int& pending = *pending_flag;
   const int p = g.p, nb = g.nb, bx = g.bx;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-
-  // blocks with a single possible winner are decided without a predictor
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
     uint32_t w = kOpen;
     if (recs[b].count == 1) {
@@ -657,11 +772,6 @@ __device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __r
     st[b] = w;
   }
   __syncthreads();
-
-  // Sweep until every block is decided.  Each sweep decides at least the
-  // first open block in raster order (its neighbours all precede it), so nb
-  // sweeps always suffice.  Lanes find the ready blocks of a 64-block chunk;
-  // the wave then prices each of them together.
   for (int sweep = 0; sweep <= nb; ++sweep) {
     if (threadIdx.x == 0) pending = 0;
     __syncthreads();
@@ -683,11 +793,8 @@ __device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __r
         const uint64_t key =
             wave_block_argmin<false>(recs + bb, ovf + (size_t)bb * ovf_stride(p), p, qx, qy, lam);
         int u = 0, v = 0;
-        uint32_t sad = 0;
-        if (key != ~0ull) {
-          window_uv((uint32_t)(key & 0xFFFFu), p, &u, &v);
-          sad = (uint32_t)(key >> 32) - lam * (se_bits(u - qx) + se_bits(v - qy));
-        }
+        window_uv((uint32_t)(key & 0xFFFFu), p, &u, &v);
+        const uint32_t sad = (uint32_t)(key >> 32) - lam * (se_bits(u - qx) + se_bits(v - qy));
         if (lane == 0) st[bb] = (sad << 16) | pack_mv(u, v);
       }
     }
@@ -698,25 +805,45 @@ __device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __r
     __syncthreads();
     if (!again) break;
   }
-
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
     const int r = b / bx, c = b - r * bx;
     int px = 0, py = 0;
     median_pred(st, b, r, c, bx, &px, &py);
     const uint32_t w = st[b];
-    const int u = mv_x((uint16_t)w), v = mv_y((uint16_t)w);
-    const uint32_t sad = w >> 16;
-    const uint32_t rate = se_bits(u - px) + se_bits(v - py);
-    acbm_block_result res;
-    res.mv.x = (int16_t)u;
-    res.mv.y = (int16_t)v;
-    res.sad = sad;
-    res.j = sad + lam * rate;
-    res.rate_bits = rate;
-    res.cands = valid_count(p, c * g.bw, r * g.bh, g.bw, g.bh, g.width, g.height);
-    res.mode = ACBM_MODE_FSBM;
-    res.intra_x = recs[b].intra_x;
-    out[b] = res;
+    int_write(g, b, mv_x((uint16_t)w), mv_y((uint16_t)w), w >> 16, px, py, lam,
+              recs[b].intra_x, out + b, st + b);
+  }
+}
+
+// FSBM resolve of one frame pair by the whole group.  `st` is the pair's
+// decision state (LDS or workspace); `shared` two words of LDS.  HP:
+// half-pel precision (every block needs its predictor: anti-diagonal
+// steps); cur and ref are then the pair's frames.  Integer precision picks
+// sweeps when under a quarter of the blocks have several possible winners
+// and steps otherwise; both decide every block with its final predictor, so
+// the results do not depend on the choice.
+template <bool HP>
+__device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __restrict__ recs,
+                                             const uint16_t* __restrict__ ovf,
+                                             acbm_block_result* __restrict__ out, uint32_t lam,
+                                             uint32_t* st, int* shared,
+                                             const uint8_t* __restrict__ cur,
+                                             const uint8_t* __restrict__ ref) {
+  if constexpr (HP) {
+    resolve_pair_half(g, recs, ovf, out, lam, st, cur, ref);
+  } else {
+    if (threadIdx.x == 0) shared[1] = 0;
+    __syncthreads();
+    int multi = 0;
+    for (int b = threadIdx.x; b < g.nb; b += blockDim.x) multi += recs[b].count > 1;
+    multi = (int)wave_sum_u32((uint32_t)multi);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&shared[1], multi);
+    __syncthreads();
+    const int nmulti = __builtin_amdgcn_readfirstlane(shared[1]);
+    if (4 * nmulti < g.nb)
+      resolve_pair_sweeps(g, recs, ovf, out, lam, st, shared);
+    else
+      resolve_pair_int(g, recs, ovf, out, lam, st);
   }
 }
 
@@ -729,11 +856,11 @@ k_resolve(const KGeom g, const BlockRec* __restrict__ recs, const uint16_t* __re
           acbm_block_result* __restrict__ out, uint32_t lam, uint32_t* st_global,
           const FramePtrs fr) {
   extern __shared__ uint32_t st_lds[];
-  __shared__ int pending;
+  __shared__ int shared[2];
   const int pair = blockIdx.x;
   resolve_pair<HP>(g, recs + (size_t)pair * g.nb, ovf + (size_t)pair * g.nb * ovf_stride(g.p),
                    out + (size_t)pair * g.nb, lam,
-                   st_global ? st_global + (size_t)pair * g.nb : st_lds, &pending,
+                   st_global ? st_global + (size_t)pair * g.nb : st_lds, shared,
                    HP ? fr.f[pair + 1] : nullptr, HP ? fr.f[pair] : nullptr);
 }
 
@@ -832,7 +959,7 @@ k_half_prep(const KGeom g, const FramePtrs fr, int npairs, BlockRec* __restrict_
 __global__ void __launch_bounds__(1024)
 k_resolve_batch(const BatchJob* __restrict__ jobs, int njobs) {
   extern __shared__ uint32_t st_lds[];
-  __shared__ int pending;
+  __shared__ int shared[2];
   const uint32_t wg = blockIdx.x;
   int j = 0;
   for (int base = 0; base < njobs; base += 64) {  // jobs are sorted by pair0
@@ -851,9 +978,9 @@ k_resolve_batch(const BatchJob* __restrict__ jobs, int njobs) {
   acbm_block_result* out = J.out + (size_t)pair * g.nb;
   uint32_t* st = J.mv_ws ? J.mv_ws + (size_t)pair * g.nb : st_lds;
   if (__builtin_amdgcn_readfirstlane(J.subpel))
-    resolve_pair<true>(g, recs, ovf, out, J.lam, st, &pending, J.frames[pair + 1], J.frames[pair]);
+    resolve_pair<true>(g, recs, ovf, out, J.lam, st, shared, J.frames[pair + 1], J.frames[pair]);
   else
-    resolve_pair<false>(g, recs, ovf, out, J.lam, st, &pending, nullptr, nullptr);
+    resolve_pair<false>(g, recs, ovf, out, J.lam, st, shared, nullptr, nullptr);
 }
 
 // ---------------------------------------------------------------------------
