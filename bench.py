@@ -213,6 +213,30 @@ def halfpel_leg(torch, acbm, frames, prm, stream, steps):
     return out
 
 
+def latency_leg(torch, acbm, frames, prm, stream, reps=5):
+    """Device time of one frame pair alone (frames 30 and 31 of the sequence,
+    temporal field zero): the latency a single pair sees, which for ACBM is
+    its block-dependency path rather than throughput."""
+    out = {}
+    pair = frames[30:32]
+    for name, algo in (("fsbm", acbm.ALGO_FSBM), ("acbm", acbm.ALGO_ACBM)):
+        b = acbm.Batch(frames[0].device)
+        b.add(pair, 16, 16, 32, prm, algo)
+        ws = torch.empty(max(256, b.workspace_size()), dtype=torch.uint8, device=frames[0].device)
+        b.run(ws, stream)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            b.run(ws, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        out[name + "_pair_ms"] = float(np.median(ts))
+    return out
+
+
 def served_leg(acbm, synth, rates, seconds, nstreams=32, nfr=3):
     """Poisson arrivals of frame-pair FSBM requests over 32 streams whose
     resolution (640x480 .. 3840x2160) and p (16, 32, 64) are drawn per stream;
@@ -386,6 +410,8 @@ def main():
                                             if traffic else None),
                            "kernel": "k_search (FSBM window search, QSAD)",
                            "launch_ms": search_ms / search_n}
+    if do_f and do_a and len(frames) >= 32:
+        out["latency_one_pair"] = latency_leg(torch, acbm, frames, prm, stream)
     if args.only in (None, "halfpel"):
         out["halfpel"] = halfpel_leg(torch, acbm, frames, prm, stream, args.steps)
     if args.only in (None, "batch") and not args.no_batch:

@@ -816,6 +816,17 @@ static int device_cus() {
   return cus;
 }
 
+// Row walkers per CU: as many as fit (the default), or fewer when
+// ACBM_PRED_WALKERS_PER_CU says so; walkers on one CU share its SIMDs.
+static int walkers_per_cu() {
+  static int n = [] {
+    const char* e = std::getenv("ACBM_PRED_WALKERS_PER_CU");
+    const int v = e ? std::atoi(e) : 0;
+    return v > 0 ? v : 1 << 20;
+  }();
+  return n;
+}
+
 template <int N, int M, int NT, bool HP = false>
 static int launch_pred_nmt(const PredArgs& a, int R, size_t lds,
                            hipStream_t st) {
@@ -829,6 +840,7 @@ static int launch_pred_nmt(const PredArgs& a, int R, size_t lds,
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, lds) != hipSuccess || \
         per_cu < 1)                                                                        \
       per_cu = 1;                                                                          \
+    per_cu = std::min(per_cu, walkers_per_cu());                                           \
     /* about as many row walkers as can be resident, never more than rows */              \
     const int grid = (int)std::min<size_t>((size_t)device_cus() * per_cu,                  \
                                            (size_t)a.npairs * a.g.by);                     \

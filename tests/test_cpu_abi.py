@@ -104,3 +104,24 @@ def test_batch_argument_errors():
 def test_default_params_scale_with_block_size():
     assert acbm.default_params(16, 16, 8) == acbm.Params(8, 8, 1000, 8, 1, 4)
     assert acbm.default_params(8, 8, 8) == acbm.Params(8, 8, 250, 2, 1, 4)
+
+
+def test_stats_and_precision_argument_errors():
+    """acbm_sad_stats and the half-pel parameter are checked before any
+    device call: bad geometry or pointers, subpel other than 0/1, half-pel
+    with p > 63, and more block rows than the resolve gives threads."""
+    L = acbm.lib()
+    g = _g()
+    assert L.acbm_sad_stats(C.byref(g), FAKE, FAKE, None, None) == acbm.E_INVAL
+    assert L.acbm_sad_stats(C.byref(g), None, FAKE, FAKE, None) == acbm.E_INVAL
+    assert L.acbm_sad_stats(C.byref(_g(height=150)), FAKE, FAKE, FAKE, None) == acbm.E_SHAPE
+    bad = acbm.Params(lam=4, subpel=2).c()
+    assert L.acbm_fsbm_frame(C.byref(g), C.byref(bad), FAKE, FAKE, FAKE, FAKE, 1 << 20, None) == acbm.E_INVAL
+    wide = _g(width=192, height=192, pitch=192, p=64)
+    hp = acbm.Params(lam=4, subpel=1).c()
+    assert L.acbm_fsbm_frame(C.byref(wide), C.byref(hp), FAKE, FAKE, FAKE, FAKE, 1 << 30, None) == acbm.E_RANGE
+    assert L.acbm_acbm_frame(C.byref(wide), C.byref(hp), FAKE, FAKE, None, FAKE, FAKE, 1 << 30, None) == acbm.E_RANGE
+    tall = _g(width=8, height=8 * 1025, pitch=8, block_w=8, block_h=8, p=2)
+    assert L.acbm_fsbm_frame(C.byref(tall), C.byref(acbm.Params(lam=1).c()), FAKE, FAKE, FAKE, FAKE,
+                             1 << 30, None) == acbm.E_UNSUPPORTED
+    assert L.acbm_last_error().decode() != ""
