@@ -425,15 +425,21 @@ __device__ __forceinline__ uint64_t critical_search(const uint32_t* __restrict__
   constexpr int S = HP ? 2 : 1;
   const WindowShape& s = w.s;
   const int p = s.p, W = 2 * S * p + 1;
+  // a block whose whole window is valid masks only the padding candidates
+  const bool whole = vbox.u_min == -p && vbox.u_max == p && vbox.v_min == -p && vbox.v_max == p;
   const int tasks = s.quads * s.groups;
   uint64_t lbest = ~0ull;
 #pragma unroll 1
   for (int task = threadIdx.x; task < tasks; task += blockDim.x) {
-    const int q = task % s.quads, gi = task / s.quads;
+    const int gi = (int)__umulhi((uint32_t)task, s.qmagic);  // task / quads
+    const int q = task - gi * s.quads;
     const int u0 = s.u_lo + 4 * q, v0 = -p + R * gi;
     uint64_t acc[R];
     task_sads_ring<N, M, R>(ring, w, cb0, q, gi, cd, acc);
-    mask_invalid<R>(acc, vbox, u0, v0);
+    if (whole)
+      mask_padding<R>(acc, p, u0, v0);
+    else
+      mask_invalid<R>(acc, vbox, u0, v0);
     uint32_t ru[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) ru[i] = lam * se_bits(S * (u0 + i) - px);
