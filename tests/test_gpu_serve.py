@@ -1,5 +1,7 @@
 """Served requests: each result equals the same frame pair run alone, however
 requests of different streams interleave on the GPU, and error paths."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -23,7 +25,16 @@ def _streams():
         ([f[:96, :128].copy() for f in sc.frames[:4]], 8, 5, 4, acbm.ALGO_FSBM),
         ([f[:256, :320].copy() for f in hd.frames], 16, 16, 8, acbm.ALGO_PBM),
         ([f[32:176, 16:192].copy() for f in sc.frames], 16, 9, 2, acbm.ALGO_ACBM),
+        # half-pel precision (vectors and the stream's resident field in half-pel units)
+        ([f[:144, :176].copy() for f in sc.frames], 16, 7, 8, ("half", acbm.ALGO_ACBM)),
     ]
+
+
+def _prm(blk, lam, algo):
+    p = acbm.default_params(blk, blk, lam)
+    if isinstance(algo, tuple):
+        return dataclasses.replace(p, subpel=1), algo[1]
+    return p, algo
 
 
 def _alone(frames, blk, p, prm, algo):
@@ -42,27 +53,29 @@ def test_served_results_equal_alone_in_a_mix():
         for t in range(nmax):  # interleave the streams frame by frame
             for sid, (frames, blk, p, lam, algo) in enumerate(streams):
                 if t < len(frames):
-                    prm = acbm.default_params(blk, blk, lam)
-                    tickets[(sid, t)] = srv.submit(sid, frames[t], blk, blk, p, prm, algo)
+                    prm, a = _prm(blk, lam, algo)
+                    tickets[(sid, t)] = srv.submit(sid, frames[t], blk, blk, p, prm, a)
         got = {k: srv.wait(v, timeout_us=60_000_000) for k, v in tickets.items()}
         st = srv.stats()
     finally:
         srv.close()
     for sid, (frames, blk, p, lam, algo) in enumerate(streams):
-        prm = acbm.default_params(blk, blk, lam)
+        prm, a = _prm(blk, lam, algo)
         assert got[(sid, 0)] is None  # the first frame only becomes the reference
-        alone = _alone(frames, blk, p, prm, algo)
+        alone = _alone(frames, blk, p, prm, a)
         for t in range(1, len(frames)):
             assert np.array_equal(got[(sid, t)], alone[t - 1]), (sid, t)
-    # and one stream against the oracle directly
-    frames, blk, p, lam, algo = streams[0]
-    prm = acbm.default_params(blk, blk, lam)
-    oprm = oracle.Params(lam=prm.lam, qp=prm.qp, alpha=prm.alpha, beta=prm.beta,
-                         gamma_num=prm.gamma_num, gamma_den=prm.gamma_den)
-    want = oracle.sequence(frames, blk, blk, p, oprm, oracle.ACBM)
-    for t in range(1, len(frames)):
-        for f in ("mv_x", "mv_y", "sad", "j", "rate_bits", "cands", "mode", "intra_x"):
-            assert np.array_equal(got[(0, t)][f].astype(np.int64), want[t - 1][f].astype(np.int64)), (t, f)
+    # streams 0, 1 and the half-pel one against the oracle directly
+    for sid in (0, 1, len(streams) - 1):
+        frames, blk, p, lam, algo = streams[sid]
+        prm, a = _prm(blk, lam, algo)
+        oprm = oracle.Params(lam=prm.lam, qp=prm.qp, alpha=prm.alpha, beta=prm.beta,
+                             gamma_num=prm.gamma_num, gamma_den=prm.gamma_den, subpel=prm.subpel)
+        want = oracle.sequence(frames, blk, blk, p, oprm, a)
+        for t in range(1, len(frames)):
+            for f in ("mv_x", "mv_y", "sad", "j", "rate_bits", "cands", "mode", "intra_x"):
+                assert np.array_equal(got[(sid, t)][f].astype(np.int64),
+                                      want[t - 1][f].astype(np.int64)), (sid, t, f)
     total = sum(len(s[0]) - 1 for s in streams)
     assert st["completed"] == total
     assert 0 < st["p50_us"] <= st["p99_us"]
