@@ -95,6 +95,32 @@ def cpu_baseline(wl, prm_oracle):
             "seconds": round(dt, 2)}
 
 
+def cpu_baseline_parallel(wl, prm_oracle, threads=16):
+    """The same oracle, unchanged, on several frame pairs at once: one pair
+    per thread (ctypes releases the interpreter lock around each C call), as
+    many threads as the host's share of cores allows, at most 16."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    n = max(1, min(threads, os.cpu_count() or 1, len(wl.frames) - 1))
+
+    def one(t):
+        cur, ref = wl.frames[t], wl.frames[t - 1]
+        f = oracle.fsbm_frame(cur, ref, 16, 16, 32, prm_oracle)
+        a = oracle.acbm_frame(cur, ref, 16, 16, 32, prm_oracle)
+        return (int(f["cands"].astype(np.int64).sum()) + int(a["cands"].astype(np.int64).sum())) * 256
+
+    oracle.se_bits(0)  # load the library before the threads start
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=n) as ex:
+        evals = sum(ex.map(one, range(1, n + 1)))
+    dt = time.perf_counter() - t0
+    return {"value": evals / dt, "unit": "candidate-pixel SAD evals/s", "cores": n, "kind": "oracle",
+            "sample": f"FSBM + ACBM of pairs 1..{n} of the 1920x1088 p=32 sequence, one pair per "
+                      f"thread, {dt:.1f} s, {evals / 1e9:.2f} G evals",
+            "seconds": round(dt, 2)}
+
+
 def batched_leg(torch, acbm, synth, dev, reps=5):
     """64 sequences x 8 frames of mixed resolution, p and block size (FSBM):
     the graph-recorded batch against the eager batch call and against one
@@ -424,6 +450,9 @@ def main():
                                                              beta=prm.beta, gamma_num=prm.gamma_num,
                                                              gamma_den=prm.gamma_den))
         out["cpu_baseline"]["host"] = platform.processor() or platform.machine()
+        out["cpu_baseline_parallel"] = cpu_baseline_parallel(
+            wl, oracle.Params(lam=prm.lam, qp=prm.qp, alpha=prm.alpha, beta=prm.beta,
+                              gamma_num=prm.gamma_num, gamma_den=prm.gamma_den))
     print(json.dumps(out), flush=True)
 
 
