@@ -168,7 +168,8 @@ static SearchPlan plan_for(int N, int M, int p, int R, int max_threads, double* 
   // kWaveFixed: per-wave cost of the window load, the scalar load of the
   // current block and the epilogue reductions, fitted to an R sweep of the
   // 1920x1088 p = 32 search on MI355X (R = 6 on 192 threads fastest at
-  // 5.05 ms, then R = 5 and R = 11; R = 3, 4 and 16 slowest).
+  // 4.77 ms, then R = 5 at 5.15 ms and R = 11 at 5.42 ms; R = 8 5.94 ms and
+  // R = 4 6.74 ms).
   constexpr double kWaveFixed = 400.0;
   *cost = (double)(threads / 64) * rounds * (std::max(valu, ldsc) + kWaveFixed);
   return SearchPlan{R, threads, lds};

@@ -12,13 +12,19 @@
 //  k_resolve one workgroup per frame pair.  The predictor of a block depends
 //            on the final vectors of its left, top and top-right neighbours,
 //            so the argmin of J is sequential in raster order; the kernel
-//            resolves every block as soon as those three are known (blocks
-//            with a single possible winner need no predictor at all).
+//            resolves every block as soon as those three are known, either
+//            in sweeps (blocks with a single possible winner need no
+//            predictor at all) or, when many blocks have several, in
+//            anti-diagonal steps with one block per lane.
+// With half-pel precision k_half_prep first computes the half-pel SADs
+// around the possible winners of few-winner blocks, and the resolve adds the
+// 8 half-pel positions around each integer winner.
 //
 // Pruning bound (exact): R >= 2 for every candidate and R <= Rmax =
-// 2*se(2p), so the winner has J <= SAD_min + lambda*Rmax while any candidate
-// has J >= SAD + 2*lambda; only candidates with
-// SAD <= SAD_min + lambda*(Rmax - 2) can win (ties included).
+// 2*se(2p) (2*se(4p) in half-pel units), so the winner has
+// J <= SAD_min + lambda*Rmax while any candidate has J >= SAD + 2*lambda;
+// only candidates with SAD <= SAD_min + lambda*(Rmax - 2) can win (ties
+// included).
 #include <hip/hip_runtime.h>
 
 #include "acbm_device.h"
