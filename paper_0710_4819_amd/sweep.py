@@ -131,6 +131,57 @@ def table(rows: list, setting: str | None = None) -> str:
     return "\n".join(lines)
 
 
+TABLE1_QPS = (30, 28, 26, 24, 22, 20, 18, 16)
+
+
+def table1(sequences: dict, qps=TABLE1_QPS, steps=(1, 3), fps=30, device="cuda:0") -> dict:
+    """Table 1's layout on the given sequences (name -> Workload with
+    16x16 blocks and p = 15): average candidate positions per macroblock of
+    ACBM with the paper's thresholds, half-pel precision, lambda = Qp, at
+    each Qp and frame rate, next to half-pel FSBM's count.  Every job of
+    every sequence runs in one acbm_batch call."""
+    dev = torch.device(device)
+    batch = acbm.Batch(dev)
+    keys = []
+    for name, wl in sequences.items():
+        fr = [torch.from_numpy(np.ascontiguousarray(f)).to(dev) for f in wl.frames]
+        for step in steps:
+            seq = fr[::step]
+            for qp in qps:
+                prm = acbm.Params(lam=qp, qp=qp, alpha=PAPER.alpha, beta=PAPER.beta,
+                                  gamma_num=PAPER.gamma_num, gamma_den=PAPER.gamma_den, subpel=1)
+                batch.add(seq, wl.block_w, wl.block_h, wl.p, prm, acbm.ALGO_ACBM)
+                keys.append((name, "ACBM", qp, step))
+            batch.add(seq, wl.block_w, wl.block_h, wl.p,
+                      acbm.Params(lam=qps[-1], qp=qps[-1], subpel=1), acbm.ALGO_FSBM)
+            keys.append((name, "FSBM", qps[-1], step))
+    outs = batch.run()
+    torch.cuda.synchronize(dev)
+    table = {}
+    for (name, algo, qp, step), out in zip(keys, outs):
+        r = acbm.to_numpy(out)
+        table[(name, algo, qp, fps / step)] = {
+            "cands_per_block": float(r["cands"].astype(np.float64).mean()),
+            "critical_frac": float((r["mode"] == acbm.MODE_CRITICAL).mean()),
+            "interior_cands_max": int(r["cands"][:, 1:-1, 1:-1].max()) if algo == "FSBM" else None,
+        }
+    return table
+
+
+def table1_text(table: dict) -> str:
+    names = sorted({k[0] for k in table})
+    rates = sorted({k[3] for k in table}, reverse=True)
+    qps = sorted({k[2] for k in table if k[1] == "ACBM"}, reverse=True)
+    head = "Qp   " + "".join(f"{n + ' ' + str(int(f)) + 'fps':>20s}" for n in names for f in rates)
+    lines = [head]
+    for qp in qps:
+        lines.append(f"{qp:<5d}" + "".join(f"{table[(n, 'ACBM', qp, f)]['cands_per_block']:20.1f}"
+                                           for n in names for f in rates))
+    fs = [v["interior_cands_max"] for k, v in table.items() if k[1] == "FSBM"]
+    lines.append(f"FSBM positions per interior macroblock: {max(fs)}")
+    return "\n".join(lines)
+
+
 def main(argv=None):
     import argparse
     import json
@@ -140,7 +191,16 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="ACBM threshold / frame-rate sweep on the GPU")
     ap.add_argument("--json", help="write every row here")
     ap.add_argument("--frames", type=int, default=30)
+    ap.add_argument("--table1", action="store_true",
+                    help="Table 1's layout on synthetic QCIF sequences (p = 15, half-pel)")
     a = ap.parse_args(argv)
+    if a.table1:
+        seqs = {k: synth.qcif_scene(k, nframes=a.frames) for k in ("smooth", "textured")}
+        t0 = time.perf_counter()
+        tab = table1(seqs)
+        print(f"{len(tab)} jobs in one batch: {time.perf_counter() - t0:.2f} s")
+        print(table1_text(tab))
+        return
     wl = synth.cif_scene(nframes=a.frames)
     t0 = time.perf_counter()
     rows = run(wl.frames, wl.block_w, wl.block_h, wl.p)

@@ -250,6 +250,22 @@ def cif_scene(nframes=30, lam=8, seed=2000, with_truth=False) -> Workload:
     return Workload("cif_scene", frames, 16, 16, 16, lam, lam, truth, {"pan": pan})
 
 
+def qcif_scene(kind: str, nframes=30, seed=7000) -> Workload:
+    """QCIF 176x144, 16x16 blocks, p = 15 (Section 4's setting) in two
+    characters that stand in for the paper's test sequences: "smooth" (soft
+    texture, sigma 3, slow motion: 2 objects, |v| <= 2, pan 1) and
+    "textured" (fine texture, sigma 1, fast motion: 5 objects, |v| <= 8,
+    pan up to 4).  Noise sigma 2."""
+    if kind == "smooth":
+        frames, _, _, _ = moving_scene(144, 176, nframes, 2, (32, 64), 2, 1, seed, blur_sigma=3.0)
+    elif kind == "textured":
+        frames, _, _, _ = moving_scene(144, 176, nframes, 5, (24, 64), 8, 4, seed + 500,
+                                       blur_sigma=1.0)
+    else:
+        raise ValueError(f"unknown kind {kind}")
+    return Workload(f"qcif_{kind}", frames, 16, 16, 15, 0, 0, None, {"kind": kind})
+
+
 def hd_scene(nframes=60, lam=8, seed=3000, with_truth=False) -> Workload:
     """1920x1088, 16x16 blocks, p = 32: pan of 1-3 px/frame, 16 rectangles of
     64-256 px with velocities in [-24, 24]^2 (relative motion stays within p),

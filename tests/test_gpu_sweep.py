@@ -72,3 +72,39 @@ def test_full_grid_trends_and_paper_rows_equal_oracle():
     for step in (1, 3):
         assert paper[(32, step, "ACBM")]["critical_frac"] < paper[(2, step, "ACBM")]["critical_frac"]
     say(sweep.table(rows))
+
+
+def test_table1_layout_equals_oracle_and_shows_its_trends():
+    """Table 1's measure at the paper's setting (QCIF, 16x16, p = 15, half-pel,
+    lambda = Qp, alpha, beta, gamma = 1000, 8, 1/4) on two synthetic
+    sequences: every job equals the oracle; half-pel FSBM evaluates 969
+    positions per interior macroblock (at 30 fps on every one); and ACBM costs
+    less at larger Qp, more at 10 fps than at 30 fps, and more on the textured
+    sequence."""
+    seqs = {k: synth.qcif_scene(k, nframes=13) for k in ("smooth", "textured")}
+    qps = (30, 22, 16)
+    say("[table1] qcif smooth/textured, 13 frames, Qp 30/22/16, 30 and 10 fps")
+    tab = sweep.table1(seqs, qps=qps)
+    for (name, algo, qp, fps), row in tab.items():
+        step = 1 if fps == 30 else 3
+        prm = oracle.Params(lam=qp, qp=qp, alpha=1000, beta=8, gamma_num=1, gamma_den=4, subpel=1)
+        if algo == "FSBM":
+            prm = oracle.Params(lam=qp, qp=qp, subpel=1)
+        want = oracle.sequence(seqs[name].frames[::step], 16, 16, 15, prm, ALGO[algo])
+        assert row["cands_per_block"] == float(want["cands"].astype(np.float64).mean()), (name, algo, qp, fps)
+        if algo == "FSBM":
+            # 961 integer + 8 half-pel positions; at 10 fps a winner at the
+            # window edge loses the half-pel neighbours beyond +-p
+            assert row["interior_cands_max"] == 969
+            if fps == 30:
+                assert (want["cands"][:, 1:-1, 1:-1] == 969).all()
+    acb = {(n, qp, f): v["cands_per_block"] for (n, a, qp, f), v in tab.items() if a == "ACBM"}
+    for n in seqs:
+        for f in (30.0, 10.0):
+            assert acb[(n, 30, f)] <= acb[(n, 22, f)] <= acb[(n, 16, f)], (n, f)
+        for qp in qps:
+            assert acb[(n, qp, 10.0)] >= acb[(n, qp, 30.0)], (n, qp)
+    for qp in qps:
+        for f in (30.0, 10.0):
+            assert acb[("textured", qp, f)] > acb[("smooth", qp, f)]
+    say(sweep.table1_text(tab))
