@@ -884,8 +884,16 @@ static int row_threads() {
 
 // Row blocking R of the critical search: the least issue time per lane,
 // rounds * (QSAD cycles of a task + its loads and pricing), among the R
-// whose ring fits in LDS.  ACBM_PRED_R overrides.
-static int pick_rows(const KGeom& g, int nt) {
+// whose ring fits in LDS.  When a launch has more block rows than the
+// device has CUs, walkers share CUs and, for 16-wide blocks, R stays <= 3:
+// under the register budget of 3 waves per SIMD the R >= 4 kernels sit at
+// 165-168 VGPRs and spill for R = 4, 6 and 8; on the 1920x1088 p = 32 ACBM
+// sequence (59 pairs) R = 3 was fastest (6.9 ms; R = 1 7.3, 2 8.1, 4 10.5,
+// 5 7.4, 6 8.7, 8 11.2 ms).  A single pair (68 walkers, each alone on its
+// CU) is faster with the one-round R = 5 (2.0 against 2.6 ms).
+// ACBM_PRED_R overrides.
+static int pick_rows(const KGeom& g, int nt, uint32_t npairs) {
+  const bool shared_cus = (size_t)npairs * g.by > (size_t)device_cus();
   const char* force = std::getenv("ACBM_PRED_R");
   const int nc = g.bw / 4;
   int bestR = 0;
@@ -894,6 +902,7 @@ static int pick_rows(const KGeom& g, int nt) {
     const RingShape w = ring_for(g, R);
     if ((size_t)w.s.rows * w.stride * 4 > (size_t)lds_limit()) continue;
     if (force && std::atoi(force) != R) continue;
+    if (!force && shared_cus && g.bw == 16 && R > 3) continue;
     const long rounds = (w.s.quads * w.s.groups + nt - 1) / nt;
     const long cost = rounds * ((long)R * g.bh * nc * 16 + 8L * (R + g.bh - 1) + 160L * R);
     if (!bestR || cost < best) {
@@ -910,7 +919,7 @@ int launch_predictive(const KGeom& g, const acbm_params& prm, int algo,
   if (ws_bytes < predictive_ws_bytes(g, npairs)) return fail(ACBM_E_NOMEM, "workspace too small");
   const bool hp = prm.subpel != 0;
   const int nt = hp ? 256 : row_threads();
-  const int R = pick_rows(g, nt);
+  const int R = pick_rows(g, nt, std::min<uint32_t>(npairs, kMaxPairsPerLaunch));
   if (!R) return fail(ACBM_E_UNSUPPORTED, "search window too large for the predictive kernel");
   const uint32_t per = std::min<uint32_t>(npairs, kMaxPairsPerLaunch);
   char* base = static_cast<char*>(ws);
