@@ -13,6 +13,19 @@
 
 namespace acbm {
 
+// Loads through pointers that were themselves read from memory (frame tables,
+// job descriptors) compile to FLAT instructions, which also count against the
+// LDS counter: every barrier would then wait for them.  Frames and results
+// always live in global memory, so these accessors say so.
+template <typename T>
+__device__ __forceinline__ T ld_global(const void* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void st_global(void* p, const T& v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+
 // ---------------------------------------------------------------------------
 // Rate term (Section 2.1, vectors sent differentially, Section 2.2): bits of
 // the signed Exp-Golomb codeword of k: 1 for k = 0, 2*floor(log2|k|) + 3

@@ -143,7 +143,7 @@ __device__ __forceinline__ const uint32_t* dep_word(const PredArgs& a, const uin
 __device__ __forceinline__ uint32_t ref_dword(const uint8_t* __restrict__ ref, const KGeom& g,
                                               int x, int y) {
   if (y >= 0 && y < g.height && x >= 0 && x + 3 < g.width)
-    return *reinterpret_cast<const uint32_t*>(ref + (size_t)y * g.pitch + x);
+    return ld_global<uint32_t>(ref + (size_t)y * g.pitch + x);
   return 0u;
 }
 
@@ -528,7 +528,7 @@ k_predictive(const PredArgs a) {
     if (threadIdx.x < D) {
       const int j = threadIdx.x / NC, k = threadIdx.x % NC;
       curd[0][threadIdx.x] =
-          *reinterpret_cast<const uint32_t*>(cur + (size_t)(y0 + j) * g.pitch + 4 * k);
+          ld_global<uint32_t>(cur + (size_t)(y0 + j) * g.pitch + 4 * k);
     }
     if (threadIdx.x == 0) sh_left = kMvUnset;
     uint32_t pre_word = 0;  // dependency word of this lane (wave 0), loaded one block ahead
@@ -563,9 +563,10 @@ k_predictive(const PredArgs a) {
           const int rr = r + (lane - 5) / 3 - 1, cc = c + (lane - 5) % 3 - 1;
           if (rr >= 0 && rr < by && cc >= 0 && cc < bx) {
             if (a.prev0) {
-              const acbm_mv m = *reinterpret_cast<const acbm_mv*>(
-                  a.prev0 + (size_t)(rr * bx + cc) * a.prev0_stride);
-              val = pack_mv(m.x, m.y);
+              // acbm_mv: x in the low, y in the high 16 bits
+              const uint32_t m =
+                  ld_global<uint32_t>(a.prev0 + (size_t)(rr * bx + cc) * a.prev0_stride);
+              val = pack_mv((int16_t)(m & 0xFFFFu), (int16_t)(m >> 16));
             } else {
               val = pack_mv(0, 0);
             }
@@ -625,8 +626,7 @@ k_predictive(const PredArgs a) {
           fetch_columns<N>(nxt, w, ref, g, y0, cb0 + w.s.dws, f, nf);
           if (f < D) {
             const int j = f / NC, k = f % NC;
-            nxt_cur = *reinterpret_cast<const uint32_t*>(cur + (size_t)(y0 + j) * g.pitch + x0 +
-                                                         N + 4 * k);
+            nxt_cur = ld_global<uint32_t>(cur + (size_t)(y0 + j) * g.pitch + x0 + N + 4 * k);
           }
         }
         if (wave == 1) {  // IntraX (Section 3.1) of the current block
