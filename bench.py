@@ -122,9 +122,10 @@ def cpu_baseline_parallel(wl, prm_oracle, threads=16):
 
 
 def batched_leg(torch, acbm, synth, dev, reps=5):
-    """64 sequences x 8 frames of mixed resolution, p and block size (FSBM):
-    the graph-recorded batch against the eager batch call and against one
-    acbm_fsbm_frame call per frame pair, all on one stream, inputs resident."""
+    """64 sequences x 8 frames of mixed resolution, p and block size: the
+    graph-recorded FSBM batch against the eager batch call and against one
+    acbm_fsbm_frame call per frame pair, and the same sequences as one
+    graph-recorded ACBM batch, all on one stream, inputs resident."""
     seqs = [synth.batch_sequence(s) for s in range(64)]
     # tune each (block size, p) on the largest frame that uses it
     largest = {}
@@ -186,6 +187,19 @@ def batched_leg(torch, acbm, synth, dev, reps=5):
     evals = sum(int(r["cands"].astype(np.int64).sum()) * w.block_w * w.block_h
                 for r, w in zip(res, seqs))
     gr.close()
+    # the same sequences with ACBM: one row-walker launch per block size
+    ba = acbm.Batch(dev)
+    for w, fr, prm in zip(seqs, dframes, prms):
+        ba.add(fr, w.block_w, w.block_h, w.p, prm, acbm.ALGO_ACBM)
+    ws_a = torch.empty(max(256, ba.workspace_size()), dtype=torch.uint8, device=dev)
+    gra = acbm.BatchGraph(ba, ws_a)
+    a_ms, _ = timed(lambda: gra.launch(st), reps)
+    assert ba.status(ws_a, st) == 0, "batched ACBM dependency wait timed out"
+    res_a = [acbm.to_numpy(o) for o in ba.outs]
+    gra.close()
+    evals_a = sum(int(r["cands"].astype(np.int64).sum()) * w.block_w * w.block_h
+                  for r, w in zip(res_a, seqs))
+    crit_a = float(np.mean(np.concatenate([(r["mode"] == 3).ravel() for r in res_a])))
     return {"workload": "64 sequences x 8 frames: QCIF/CIF/1280x720/1920x1088, p 7/16/32, "
                         "16x16 and 8x8 blocks, lambda 8, FSBM",
             "pairs": sum(len(w.frames) - 1 for w in seqs), "evals": evals,
@@ -194,6 +208,9 @@ def batched_leg(torch, acbm, synth, dev, reps=5):
             "eager_batch_ms": e_ms, "per_frame_fsbm_ms": p_ms,
             "per_frame_fsbm_wall_ms": p_wall,
             "speedup_graph_vs_per_frame": p_ms / g_ms,
+            "acbm_graph_ms": a_ms, "acbm_evals": evals_a, "acbm_critical_frac": crit_a,
+            "acbm_graph_speed_vs_fsbm_graph": g_ms / a_ms,
+            "acbm_graph_speed_vs_per_frame_fsbm": p_ms / a_ms,
             "tuned_rows": {f"{k[0]}x{k[1]}_p{k[2]}": v for k, v in tuned.items()}}
 
 
@@ -226,7 +243,7 @@ def halfpel_leg(torch, acbm, frames, prm, stream, steps):
                 kern[k + "_ms_per_launch"] = ms / n
         acbm.profile_enable(False)
         if algo == acbm.ALGO_ACBM:
-            assert acbm.workspace_status(ws, stream) == 0, "half-pel ACBM dependency wait timed out"
+            assert b.status(ws, stream) == 0, "half-pel ACBM dependency wait timed out"
         r = acbm.to_numpy(res)
         ms = e0.elapsed_time(e1) / steps
         npairs = len(frames) - 1
@@ -374,7 +391,7 @@ def main():
         step()
     torch.cuda.synchronize()
     if do_a:
-        assert acbm.workspace_status(ws_a, stream) == 0, "ACBM dependency wait timed out"
+        assert ac.status(ws_a, stream) == 0, "ACBM dependency wait timed out"
 
     acbm.profile_enable(True)
     acbm.profile_reset()

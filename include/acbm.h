@@ -205,15 +205,28 @@ int acbm_batch_workspace_size(const acbm_job* jobs, size_t njobs, size_t* bytes)
  * and window-search plan; each group is one persistent full-search launch
  * over all (job, pair, block) items of its jobs plus one resolve launch
  * with a workgroup per pair, reading job tables that small kernels write
- * into `ws` first.  PBM/ACBM jobs each get their row-pipelined launch.
+ * into `ws` first.  PBM/ACBM jobs (Sections 2.2, 3.2) are grouped by block
+ * size and precision, at most 256 jobs a group; each group is one row-walker
+ * launch whose walkers take the block rows of all its jobs in level order
+ * (row r of pair t has level r + 2t), so the dependency chains of the jobs
+ * run side by side.  A PBM/ACBM job of more than 4095 pairs runs alone.
  * ws must hold acbm_batch_workspace_size bytes (per-job scratch plus the
  * tables) and must not be shared by overlapping calls. */
 int acbm_batch(const acbm_job* jobs, size_t njobs, void* ws, size_t ws_bytes, void* stream);
 
+/* Device-detected status of the last acbm_batch (or batch graph launch) of
+ * these jobs on `ws`, as acbm_workspace_status reports it for one job: 0
+ * when every PBM/ACBM block finished, ACBM_E_TIMEOUT when a dependency wait
+ * of any walker gave up.  `jobs` must describe the same batch (the layout
+ * of `ws` follows from it).  Enqueues small copies on `stream` and waits for
+ * the stream. */
+int acbm_batch_status(const acbm_job* jobs, size_t njobs, const void* ws, size_t ws_bytes,
+                      void* stream, int* status);
+
 /* A batch recorded once as a HIP graph and replayed with one launch.
  * create: validates like acbm_batch, then records exactly the sequence
  *   acbm_batch enqueues (job-table writes, the persistent FSBM groups, the
- *   PBM/ACBM launches) on a private stream and instantiates it.  Frame
+ *   PBM/ACBM walker groups) on a private stream and instantiates it.  Frame
  *   pointers, `out` arrays, parameters and `ws` are baked in: they must stay
  *   allocated at the same addresses for the graph's lifetime (their contents
  *   may change between launches).  The graph holds only kernel nodes (no

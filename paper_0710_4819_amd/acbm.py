@@ -129,6 +129,7 @@ def lib():
         L.acbm_acbm_frame.argtypes = [P(Geom), P(CParams), vp, vp, vp, vp, vp, sz, vp]
         L.acbm_batch_workspace_size.argtypes = [P(Job), sz, P(sz)]
         L.acbm_batch.argtypes = [P(Job), sz, vp, sz, vp]
+        L.acbm_batch_status.argtypes = [P(Job), sz, vp, sz, vp, P(C.c_int)]
         L.acbm_batch_graph_create.argtypes = [P(Job), sz, vp, sz, P(vp)]
         L.acbm_batch_graph_launch.argtypes = [vp, vp]
         L.acbm_batch_graph_destroy.argtypes = [vp]
@@ -295,6 +296,15 @@ class Batch:
         _check(lib().acbm_batch(self.table(), len(self.jobs), ws.data_ptr(), ws.numel(),
                                 _stream(stream)))
         return self.outs
+
+    def status(self, ws: torch.Tensor | None = None, stream=None) -> int:
+        """Device-detected status of the last run on `ws` (default: the
+        workspace of the last run): 0, or ACBM_E_TIMEOUT."""
+        ws = ws if ws is not None else self.ws
+        st = C.c_int()
+        _check(lib().acbm_batch_status(self.table(), len(self.jobs), ws.data_ptr(), ws.numel(),
+                                       _stream(stream), C.byref(st)))
+        return st.value
 
 
 class BatchGraph:

@@ -3,14 +3,17 @@
 // FSBM jobs (Section 2.3) are grouped by block size and window-search plan
 // (at most 64 jobs a group); each group runs as one full-search launch with
 // a workgroup per (job, pair, block) item, then a single resolve launch
-// takes every pair of every FSBM job at once.  The job tables those launches
-// read are written into the caller's workspace by small kernels whose
-// arguments carry the bytes, so the whole call is stream-ordered and needs
-// no host staging memory.  PBM/ACBM jobs (Sections 2.2, 3.2) keep their own
-// row-pipelined launch.
+// takes every pair of every FSBM job at once.  PBM/ACBM jobs (Sections 2.2,
+// 3.2) are grouped by block size and precision (at most 256 jobs a group);
+// each group runs as one row-walker launch whose walkers take the rows of
+// all its jobs in level order, so the jobs' dependency chains run side by
+// side.  The job tables those launches read are written into the caller's
+// workspace by small kernels whose arguments carry the bytes, so the whole
+// call is stream-ordered and needs no host staging memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <map>
 #include <tuple>
 #include <vector>
@@ -24,6 +27,11 @@ using namespace acbm;
 
 namespace {
 
+// A PBM/ACBM job joins a walker group unless its pairs exceed what a row
+// word can name; such a job runs on its own, in launches of up to
+// kMaxPairsPerLaunch pairs.
+bool grouped(const acbm_job& j) { return j.nframes - 1 <= kPredMaxPairs; }
+
 int job_ws(const acbm_job& j, size_t* bytes) {
   KGeom k;
   int rc = check_geom(&j.geom, &k);
@@ -33,10 +41,25 @@ int job_ws(const acbm_job& j, size_t* bytes) {
   switch (j.algo) {
     case ACBM_ALGO_FSBM: *bytes = align256(fsbm_ws_bytes(k, npairs)); return ACBM_OK;
     case ACBM_ALGO_PBM:
-    case ACBM_ALGO_ACBM: *bytes = align256(predictive_ws_bytes(k, npairs)); return ACBM_OK;
+    case ACBM_ALGO_ACBM:
+      // grouped: the vector words of every pair; alone: the single-job workspace
+      *bytes = grouped(j) ? align256((size_t)npairs * k.nb * sizeof(uint32_t))
+                          : align256(predictive_ws_bytes(k, npairs));
+      return ACBM_OK;
     default: return fail(ACBM_E_INVAL, "unknown algorithm");
   }
 }
+
+// PBM/ACBM jobs of one block size and precision that run as one launch.
+struct PGroup {
+  int bw = 0, bh = 0;
+  bool hp = false;
+  std::vector<size_t> job_index;  // into the caller's job array
+  uint32_t total_rows = 0;
+  size_t nptr = 0;                // frame pointers of its jobs
+  size_t off_args = 0, off_ptrs = 0;   // within the table region
+  size_t off_hdr = 0, off_order = 0;   // within the scratch region
+};
 
 // Everything one acbm_batch call enqueues, planned on the host.
 struct Class {
@@ -51,9 +74,11 @@ struct Class {
 struct Plan {
   std::vector<size_t> slice;      // workspace offset of each job
   std::vector<Class> classes;
-  std::vector<size_t> predictive; // PBM/ACBM jobs
+  std::vector<size_t> predictive; // PBM/ACBM jobs that run alone
+  std::vector<PGroup> pgroups;    // PBM/ACBM jobs that run in groups
   size_t jobs_bytes = 0;          // job slices
   size_t table_off = 0, table_bytes = 0;
+  size_t scratch_off = 0, scratch_bytes = 0;  // group headers and row orders
   size_t off_jobs = 0, off_ptrs = 0;  // within the table region
   size_t njob_fsbm = 0, nptr = 0;
   uint32_t pairs = 0;             // FSBM pairs (resolve workgroups)
@@ -61,9 +86,12 @@ struct Plan {
 };
 
 // Groups the jobs and lays out the workspace: job slices first, then the
-// table region [BatchJob per FSBM job][frame pointers].
+// table region [BatchJob per FSBM job][frame pointers][per walker group: its
+// job table, its frame pointers], then the scratch region [per walker group:
+// header, row order].
 int make_plan(const acbm_job* jobs, size_t njobs, Plan* pl) {
   std::map<std::tuple<int, int, int, int>, size_t> cls;
+  std::map<std::tuple<int, int, int>, size_t> pcls;
   size_t off = 0;
   pl->slice.resize(njobs);
   for (size_t i = 0; i < njobs; ++i) {
@@ -74,7 +102,32 @@ int make_plan(const acbm_job* jobs, size_t njobs, Plan* pl) {
     pl->slice[i] = off;
     off += b;
     if (j.algo != ACBM_ALGO_FSBM) {
-      pl->predictive.push_back(i);
+      if (!grouped(j)) {
+        pl->predictive.push_back(i);
+        continue;
+      }
+      KGeom k;
+      check_geom(&j.geom, &k);
+      const auto key = std::make_tuple(k.bw, k.bh, j.params.subpel ? 1 : 0);
+      auto it = pcls.find(key);
+      if (it != pcls.end() && pl->pgroups[it->second].job_index.size() == (size_t)kPredMaxJobs) {
+        pcls.erase(it);  // a full group: later jobs of this kind open a new one
+        it = pcls.end();
+      }
+      if (it == pcls.end()) {
+        it = pcls.emplace(key, pl->pgroups.size()).first;
+        pl->pgroups.emplace_back();
+        pl->pgroups.back().bw = k.bw;
+        pl->pgroups.back().bh = k.bh;
+        pl->pgroups.back().hp = j.params.subpel != 0;
+      }
+      PGroup& pg = pl->pgroups[it->second];
+      const uint64_t rows = (uint64_t)(j.nframes - 1) * k.by;
+      if (pg.total_rows + rows > 0xFFFFFFFFull)
+        return fail(ACBM_E_RANGE, "too many block rows in one batch group");
+      pg.total_rows += (uint32_t)rows;
+      pg.nptr += j.nframes;
+      pg.job_index.push_back(i);
       continue;
     }
     KGeom k;
@@ -124,7 +177,21 @@ int make_plan(const acbm_job* jobs, size_t njobs, Plan* pl) {
   pl->table_off = off;
   pl->off_jobs = 0;
   pl->off_ptrs = pl->off_jobs + align256(pl->njob_fsbm * sizeof(BatchJob));
-  pl->table_bytes = pl->classes.empty() ? 0 : pl->off_ptrs + align256(pl->nptr * sizeof(void*));
+  size_t t = pl->classes.empty() ? 0 : pl->off_ptrs + align256(pl->nptr * sizeof(void*));
+  size_t sc = 0;
+  for (PGroup& pg : pl->pgroups) {
+    pg.off_args = t;
+    t += align256(pg.job_index.size() * sizeof(PredArgs));
+    pg.off_ptrs = t;
+    t += align256(pg.nptr * sizeof(void*));
+    pg.off_hdr = sc;
+    sc += align256(sizeof(WsHeader));
+    pg.off_order = sc;
+    sc += align256((size_t)pg.total_rows * sizeof(uint32_t));
+  }
+  pl->table_bytes = t;
+  pl->scratch_off = pl->table_off + t;
+  pl->scratch_bytes = sc;
   return ACBM_OK;
 }
 
@@ -139,8 +206,10 @@ __global__ void k_put_table(uint64_t* __restrict__ dst, const TableChunk c, int 
   if (i < n) dst[i] = c.w[i];
 }
 
-// Fills the device pointers of the plan and enqueues the table writes.
-int write_tables(const acbm_job* jobs, Plan* pl, char* ws, hipStream_t st) {
+// Fills the device pointers of the plan, plans the walker groups and
+// enqueues the table writes.
+int write_tables(const acbm_job* jobs, Plan* pl, std::vector<PredGroupPlan>* gplans, char* ws,
+                 hipStream_t st) {
   if (!pl->table_bytes) return ACBM_OK;
   char* table = ws + pl->table_off;
   std::vector<uint64_t> host(pl->table_bytes / 8, 0);
@@ -163,6 +232,28 @@ int write_tables(const acbm_job* jobs, Plan* pl, char* ws, hipStream_t st) {
     std::memcpy(hb + pl->off_jobs + jo * sizeof(BatchJob), c.jobs.data(),
                 c.jobs.size() * sizeof(BatchJob));
     jo += c.jobs.size();
+  }
+  gplans->resize(pl->pgroups.size());
+  for (size_t gi = 0; gi < pl->pgroups.size(); ++gi) {
+    const PGroup& pg = pl->pgroups[gi];
+    std::vector<KGeom> geoms(pg.job_index.size());
+    for (size_t n = 0; n < pg.job_index.size(); ++n) check_geom(&jobs[pg.job_index[n]].geom, &geoms[n]);
+    PredGroupPlan& gp = (*gplans)[gi];
+    int rc = plan_predictive_group(geoms.data(), (int)geoms.size(), pg.hp, pg.total_rows, &gp);
+    if (rc) return rc;
+    WsHeader* hdr = reinterpret_cast<WsHeader*>(ws + pl->scratch_off + pg.off_hdr);
+    size_t pp = 0;
+    for (size_t n = 0; n < pg.job_index.size(); ++n) {
+      const acbm_job& j = jobs[pg.job_index[n]];
+      PredArgs a = predictive_args(geoms[n], j.params, (int)j.algo, gp.R, j.nframes - 1);
+      a.hdr = hdr;
+      a.words = reinterpret_cast<uint32_t*>(ws + pl->slice[pg.job_index[n]]);
+      a.frames = reinterpret_cast<const uint8_t* const*>(table + pg.off_ptrs + pp * sizeof(void*));
+      a.out = j.out;
+      std::memcpy(hb + pg.off_ptrs + pp * sizeof(void*), j.frames, j.nframes * sizeof(void*));
+      pp += j.nframes;
+      std::memcpy(hb + pg.off_args + n * sizeof(PredArgs), &a, sizeof(PredArgs));
+    }
   }
   uint64_t* dst = reinterpret_cast<uint64_t*>(table);
   const size_t nw = host.size();
@@ -203,7 +294,7 @@ int acbm_batch_workspace_size(const acbm_job* jobs, size_t njobs, size_t* bytes)
   Plan pl;
   int rc = make_plan(jobs, njobs, &pl);
   if (rc) return rc;
-  *bytes = pl.jobs_bytes + pl.table_bytes;
+  *bytes = pl.jobs_bytes + pl.table_bytes + pl.scratch_bytes;
   return ACBM_OK;
 }
 
@@ -212,15 +303,16 @@ int acbm_batch_workspace_size(const acbm_job* jobs, size_t njobs, size_t* bytes)
 namespace {
 
 // Enqueues every job of a validated batch on `st`: the job tables first,
-// then one persistent search and one resolve launch per FSBM group, then the
-// row-pipelined PBM/ACBM jobs.  Kernels only, so the sequence can be
-// recorded into a graph as it is.
+// then one persistent search and one resolve launch per FSBM group, then one
+// row-walker launch per PBM/ACBM group and the PBM/ACBM jobs that run alone.
+// Kernels only, so the sequence can be recorded into a graph as it is.
 int enqueue_batch(const acbm_job* jobs, size_t njobs, void* ws, hipStream_t st) {
   Plan pl;
   int rc = make_plan(jobs, njobs, &pl);
   if (rc) return rc;
   char* base = static_cast<char*>(ws);
-  if ((rc = write_tables(jobs, &pl, base, st))) return rc;
+  std::vector<PredGroupPlan> gplans;
+  if ((rc = write_tables(jobs, &pl, &gplans, base, st))) return rc;
   const BatchJob* all = reinterpret_cast<const BatchJob*>(base + pl.table_off + pl.off_jobs);
   size_t jo = 0;
   for (const Class& c : pl.classes) {
@@ -260,7 +352,19 @@ int enqueue_batch(const acbm_job* jobs, size_t njobs, void* ws, hipStream_t st) 
     }
     jo += c.jobs.size();
   }
-  if ((rc = launch_resolve_batch(all, (int)pl.njob_fsbm, pl.pairs, pl.lds_resolve, st))) return rc;
+  if (pl.njob_fsbm &&
+      (rc = launch_resolve_batch(all, (int)pl.njob_fsbm, pl.pairs, pl.lds_resolve, st)))
+    return rc;
+  for (size_t gi = 0; gi < pl.pgroups.size(); ++gi) {
+    const PGroup& pg = pl.pgroups[gi];
+    rc = launch_predictive_group(
+        pg.bw, pg.bh, pg.hp, gplans[gi],
+        reinterpret_cast<const PredArgs*>(base + pl.table_off + pg.off_args),
+        (int)pg.job_index.size(),
+        reinterpret_cast<uint32_t*>(base + pl.scratch_off + pg.off_order),
+        reinterpret_cast<WsHeader*>(base + pl.scratch_off + pg.off_hdr), pg.total_rows, st);
+    if (rc) return rc;
+  }
   for (size_t i : pl.predictive) {
     const acbm_job& j = jobs[i];
     KGeom k;
@@ -321,6 +425,33 @@ int acbm_batch_graph_create(const acbm_job* jobs, size_t njobs, void* ws, size_t
   e = hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0);
   if (e != hipSuccess) return hip_fail(e, "instantiating the batch graph");
   *out = gr.release();
+  return ACBM_OK;
+}
+
+int acbm_batch_status(const acbm_job* jobs, size_t njobs, const void* ws, size_t ws_bytes,
+                      void* stream, int* status) {
+  if (!jobs || !ws || !status) return fail(ACBM_E_INVAL, "jobs, workspace or status is NULL");
+  Plan pl;
+  int rc = make_plan(jobs, njobs, &pl);
+  if (rc) return rc;
+  if (ws_bytes < pl.jobs_bytes + pl.table_bytes + pl.scratch_bytes)
+    return fail(ACBM_E_NOMEM, "workspace too small");
+  // headers: one per walker group, and at the start of each solo job's slice
+  const char* base = static_cast<const char*>(ws);
+  std::vector<const char*> at;
+  for (const PGroup& pg : pl.pgroups) at.push_back(base + pl.scratch_off + pg.off_hdr);
+  for (size_t i : pl.predictive) at.push_back(base + pl.slice[i]);
+  std::vector<uint32_t> st(at.size(), 0);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  for (size_t k = 0; k < at.size() && e == hipSuccess; ++k)
+    e = hipMemcpyAsync(&st[k], at[k] + offsetof(WsHeader, status), sizeof(uint32_t),
+                       hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "reading the batch headers");
+  *status = ACBM_OK;
+  for (uint32_t v : st)
+    if (v) *status = ACBM_E_TIMEOUT;
   return ACBM_OK;
 }
 

@@ -161,4 +161,57 @@ int launch_predictive(const KGeom& g, const acbm_params& prm, int algo,
                       const uint8_t* const* frames, uint32_t npairs, const acbm_mv* prev_field,
                       void* ws, size_t ws_bytes, acbm_block_result* out, hipStream_t s);
 
+// Row walkers (PBM/ACBM) over several jobs in one launch.  Every job of a
+// group has the same block size and precision; the walkers take the rows of
+// all jobs from one ticket counter in level order (row r of pair t has level
+// r + 2t), so the chains of the jobs run side by side.
+//
+// Circular window of the walkers: absolute dword column a lives at a & (cw-1),
+// and columns 0 .. N/4+1 again at cw .. cw+N/4+1; rows are `stride` dwords
+// apart (odd).
+struct RingShape {
+  WindowShape s;
+  int cw;
+  int stride;
+};
+
+// One job as the walkers read it (device memory).
+struct PredArgs {
+  KGeom g;
+  RingShape w;
+  int algo;
+  uint32_t lam;
+  uint64_t c1_rhs;        // N*M*(alpha + beta*qp^2), saturated
+  uint32_t gamma_num, gamma_den;
+  int npairs;
+  int row_levels;         // (by-1) + 2(npairs-1) + 1
+  const uint8_t* prev0;   // temporal field of pair 0 (acbm_mv at byte stride), or null
+  int prev0_stride;
+  WsHeader* hdr;          // ticket and status, shared by the jobs of a launch
+  uint32_t* words;        // [npairs][nb] published vectors
+  const uint8_t* const* frames;  // [npairs+1] frame pointers
+  acbm_block_result* out;
+};
+
+// Row words of the merged ticket order: job (8 bits), pair (12), row (12).
+constexpr int kPredMaxJobs = 256;
+constexpr uint32_t kPredMaxPairs = 4095;
+
+struct PredGroupPlan {
+  int R = 0;        // row blocking of the critical search
+  int threads = 0;  // threads per walker
+  size_t lds = 0;   // dynamic LDS bytes (the largest ring of the group)
+};
+// Plans a group from its jobs' geometries (same block size) and its row count.
+int plan_predictive_group(const KGeom* geoms, int n, bool hp, size_t total_rows,
+                          PredGroupPlan* pl);
+// The fields of a job that do not point into device memory.
+PredArgs predictive_args(const KGeom& g, const acbm_params& prm, int algo, int R,
+                         uint32_t npairs);
+// Clears the jobs' vector words, writes the merged row order and resets the
+// header (setup kernel), then runs the walkers over every row.
+int launch_predictive_group(int bw, int bh, bool hp, const PredGroupPlan& pl,
+                            const PredArgs* jobs, int njobs, uint32_t* order, WsHeader* hdr,
+                            uint32_t total_rows, hipStream_t s);
+
 }  // namespace acbm

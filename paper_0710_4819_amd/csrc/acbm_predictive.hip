@@ -54,69 +54,71 @@ constexpr uint32_t kSpinLimit = 1u << 22;
 #define ACBM_PRED_WAVES 3  // waves per SIMD the register budget must allow
 #endif
 
-// Circular window: absolute dword column a lives at a & (cw-1), and columns
-// 0 .. N/4+1 again at cw .. cw+N/4+1; rows are `stride` dwords apart (odd).
-struct RingShape {
-  WindowShape s;
-  int cw;
-  int stride;
-};
-
-struct PredArgs {
-  KGeom g;
-  RingShape w;
-  int algo;
-  uint32_t lam;
-  uint64_t c1_rhs;        // N*M*(alpha + beta*qp^2), saturated
-  uint32_t gamma_num, gamma_den;
-  int npairs;
-  int row_levels;         // (by-1) + 2(npairs-1) + 1
-  const uint8_t* prev0;   // temporal field of pair 0 (acbm_mv at byte stride), or null
-  int prev0_stride;
-  WsHeader* hdr;
-  uint32_t* row_order;    // [npairs*by] ticket -> (t << 16) | r
-  uint32_t* words;        // [npairs][nb] published vectors
-  const uint8_t** frames; // [npairs+1] frame pointers (filled by the setup kernel)
-  acbm_block_result* out;
-};
-
 // Rows (t, r) with r + 2t = k.
 __host__ __device__ inline int row_tlo(int k, int by) { return max(0, (k - (by - 1) + 1) / 2); }
 __host__ __device__ inline int row_thi(int k, int npairs) { return min(npairs - 1, k / 2); }
 
-// Prepares the workspace of one launch: row order, cleared vector words,
-// ticket and status.  (A kernel rather than hipMemsetAsync so that the
-// sequence can be captured in a graph.)
-__global__ void k_pred_setup(PredArgs a, FramePtrs fr) {
+__host__ __device__ inline uint32_t row_word(int job, int t, int r) {
+  return ((uint32_t)job << 24) | ((uint32_t)t << 12) | (uint32_t)r;
+}
+
+// Rows of a job (by block rows, npairs pairs) with level below k.
+__device__ inline uint32_t rows_below(int k, int by, int npairs) {
+  uint32_t n = 0;
+  for (int t = 0; t < npairs && 2 * t < k; ++t) n += (uint32_t)min(by, k - 2 * t);
+  return n;
+}
+
+// Prepares one launch over `njobs` jobs: cleared vector words, the merged
+// row order and the header.  The order lists the rows by level and, within
+// a level, by job and pair, so every row comes after the rows it reads.
+// Grid: y = job; x spans the job's words and rows.  (A kernel rather than
+// hipMemsetAsync so that the sequence can be captured in a graph.)
+__global__ void k_pred_setup(const PredArgs* __restrict__ jobs, int njobs,
+                             uint32_t* __restrict__ order, WsHeader* __restrict__ hdr) {
+  const int j = blockIdx.y;
+  const PredArgs& a = jobs[j];
+  const int by = a.g.by;
   const size_t nw = (size_t)a.npairs * a.g.nb;
-  if (blockIdx.x == 0 && threadIdx.x == 0)
-    for (int k = 0; k <= a.npairs; ++k) a.frames[k] = fr.f[k];
+  const size_t nrows = (size_t)a.npairs * by;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
        i += (size_t)gridDim.x * blockDim.x)
-    a.words[i] = 0;
-  if (blockIdx.x == 0) {
-    const int by = a.g.by;
-    for (int k = threadIdx.x; k < a.row_levels; k += blockDim.x) {
-      int off = 0;  // rows in levels before k
-      for (int q = 0; q < k; ++q) off += max(0, row_thi(q, a.npairs) - row_tlo(q, by) + 1);
-      for (int t = row_tlo(k, by); t <= row_thi(k, a.npairs); ++t)
-        a.row_order[off++] = ((uint32_t)t << 16) | (uint32_t)(k - 2 * t);
+    st_global<uint32_t>(a.words + i, 0u);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nrows;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int t = (int)(i / by), r = (int)(i % by), k = r + 2 * t;
+    uint32_t pos = (uint32_t)(t - row_tlo(k, by));
+    for (int q = 0; q < njobs; ++q) {
+      const int bq = jobs[q].g.by, nq = jobs[q].npairs;
+      pos += rows_below(k, bq, nq);
+      if (q < j) pos += (uint32_t)max(0, row_thi(k, nq) - row_tlo(k, bq) + 1);
     }
-    if (threadIdx.x == 0) {
-      a.hdr->ticket = 0;
-      a.hdr->status = 0;
-    }
+    order[pos] = row_word(j, t, r);
+  }
+  if (j == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+    hdr->ticket = 0;
+    hdr->status = 0;
   }
 }
 
+// The job table and frame pointers of a single-job launch, written on the
+// stream from kernel arguments.
+__global__ void k_pred_put_job(PredArgs a, FramePtrs fr, PredArgs* __restrict__ dst,
+                               const uint8_t** __restrict__ frames) {
+  if (threadIdx.x <= (unsigned)a.npairs) frames[threadIdx.x] = fr.f[threadIdx.x];
+  if (threadIdx.x == 0) *dst = a;
+}
+
+// Published words and the header live in global memory (see ld_global).
+typedef __attribute__((address_space(1))) uint32_t gu32;
 __device__ __forceinline__ uint32_t load_word(const uint32_t* w) {
-  return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load((const gu32*)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void store_word(uint32_t* w, uint32_t v) {
-  __hip_atomic_store(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((gu32*)w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint32_t status_of(const WsHeader* h) {
-  return __hip_atomic_load(&h->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load((const gu32*)&h->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Published word lane `lane` waits for at block (t, r, c), or null: lanes
@@ -467,22 +469,20 @@ __device__ __forceinline__ uint64_t critical_search(const uint32_t* __restrict__
 __device__ __forceinline__ void write_result(acbm_block_result* out, uint32_t* word, int u, int v,
                                              uint32_t j, uint32_t rate, uint32_t lam,
                                              uint32_t cands, uint32_t mode, uint32_t intra) {
-  acbm_block_result res;
-  res.mv.x = (int16_t)u;
-  res.mv.y = (int16_t)v;
-  res.sad = j - lam * rate;
-  res.j = j;
-  res.rate_bits = rate;
-  res.cands = cands;
-  res.mode = mode;
-  res.intra_x = intra;
-  *out = res;
+  // acbm_block_result as two 16-byte stores: mv (x low, y high), sad, j,
+  // rate_bits | cands, mode, intra_x (u64 at byte 24)
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  typedef __attribute__((address_space(1))) u32x4 gu32x4;
+  gu32x4* o = (gu32x4*)out;
+  o[0] = u32x4{((uint32_t)v << 16) | ((uint32_t)u & 0xFFFFu), j - lam * rate, j, rate};
+  o[1] = u32x4{cands, mode, intra, 0u};
   store_word(word, kReady | pack_mv(u, v));
 }
 
 template <int N, int M, int R, int NT, bool HP>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ACBM_PRED_WAVES)))
-k_predictive(const PredArgs a) {
+k_predictive(const PredArgs* __restrict__ jobs, const uint32_t* __restrict__ order,
+             WsHeader* __restrict__ hdr, uint32_t total_rows) {
   extern __shared__ uint32_t ring[];
   constexpr int D = M * N / 4;
   constexpr int NC = N / 4;
@@ -492,35 +492,36 @@ k_predictive(const PredArgs a) {
   __shared__ int16_t cu[kMaxCands], cv[kMaxCands];
   __shared__ uint64_t nbr[kMaxCands][3];
   __shared__ uint32_t sadh[kMaxCands], sadr[8];  // half-pel SADs: predictors, ring
-  __shared__ int sh_row, sh_abort, sh_np, sh_px, sh_py;
+  __shared__ uint32_t sh_row;
+  __shared__ int sh_abort, sh_np, sh_px, sh_py;
   __shared__ uint32_t sh_intra;
   __shared__ uint16_t sh_left;
 
-  const KGeom& g = a.g;
-  const RingShape& w = a.w;
-  const int p = g.p, bx = g.bx, by = g.by, nb = g.nb;
-  const int W = 2 * (HP ? 2 : 1) * p + 1;  // key raster width (half-pel window with HP)
-  const uint32_t total_rows = (uint32_t)a.npairs * by;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int f = (int)threadIdx.x - 64, nf = NT - 64;  // fetching lanes: waves 1..
 
   for (;;) {
     if (threadIdx.x == 0) {
-      const uint32_t tk = atomicAdd(&a.hdr->ticket, 1u);
-      sh_row = tk < total_rows ? (int)a.row_order[tk] : -1;
-      sh_abort = status_of(a.hdr) != 0;
+      const uint32_t tk = atomicAdd(&hdr->ticket, 1u);
+      sh_row = tk < total_rows ? order[tk] : 0xFFFFFFFFu;
+      sh_abort = status_of(hdr) != 0;
     }
     __syncthreads();
     // LDS words are uniform; readfirstlane lets the compiler see that, so the
     // exits of this loop (which contains barriers) stay uniform branches
-    const int row_word = __builtin_amdgcn_readfirstlane(sh_row);
-    if (row_word < 0 || __builtin_amdgcn_readfirstlane(sh_abort)) return;
-    const int t = row_word >> 16;
-    const int r = row_word & 0xFFFF;
+    const uint32_t rw = __builtin_amdgcn_readfirstlane(sh_row);
+    if (rw == 0xFFFFFFFFu || __builtin_amdgcn_readfirstlane(sh_abort)) return;
+    const PredArgs& a = jobs[rw >> 24];
+    const int t = (int)((rw >> 12) & 0xFFFu);
+    const int r = (int)(rw & 0xFFFu);
+    const KGeom& g = a.g;
+    const RingShape& w = a.w;
+    const int p = g.p, bx = g.bx, by = g.by, nb = g.nb;
+    const int W = 2 * (HP ? 2 : 1) * p + 1;  // key raster width (half-pel window with HP)
     const int y0 = r * M;
-    const uint8_t* __restrict__ ref = a.frames[t];
-    const uint8_t* __restrict__ cur = a.frames[t + 1];
+    const uint8_t* __restrict__ ref = ld_global<const uint8_t*>(a.frames + t);
+    const uint8_t* __restrict__ cur = ld_global<const uint8_t*>(a.frames + t + 1);
     uint32_t* __restrict__ words = a.words + (size_t)t * nb;
 
     // first block of the row: its whole window and its current block
@@ -577,7 +578,7 @@ k_predictive(const PredArgs a) {
         for (;;) {
           if (dw && !(word & kReady)) word = load_word(dw);
           if (__all(!dw || (word & kReady))) break;
-          if (++spins > kSpinLimit || ((spins & 255) == 0 && status_of(a.hdr))) {
+          if (++spins > kSpinLimit || ((spins & 255) == 0 && status_of(hdr))) {
             failed = true;
             break;
           }
@@ -619,7 +620,7 @@ k_predictive(const PredArgs a) {
           sh_px = px;
           sh_py = py;
           sh_abort = failed;
-          if (failed) atomicOr(&a.hdr->status, kStatusSpinTimeout);
+          if (failed) atomicOr(&hdr->status, kStatusSpinTimeout);
         }
       } else {
         if (more) {
@@ -785,11 +786,14 @@ k_predictive(const PredArgs a) {
 // ---------------------------------------------------------------------------
 static int row_levels(const KGeom& g, int npairs) { return (g.by - 1) + 2 * (npairs - 1) + 1; }
 
+// Workspace of the single-job calls, reused by each launch of up to
+// kMaxPairsPerLaunch pairs: header, row order, vector words, frame pointers
+// and the one-entry job table.
 size_t predictive_ws_bytes(const KGeom& g, uint32_t npairs) {
   const uint32_t per = std::min<uint32_t>(npairs, kMaxPairsPerLaunch);
   return align256(sizeof(WsHeader)) + align256((size_t)per * g.by * sizeof(uint32_t)) +
          align256((size_t)per * g.nb * sizeof(uint32_t)) +
-         align256((size_t)(kMaxPairsPerLaunch + 1) * sizeof(void*));
+         align256((size_t)(kMaxPairsPerLaunch + 1) * sizeof(void*)) + align256(sizeof(PredArgs));
 }
 
 template <int N, int M>
@@ -808,6 +812,8 @@ static RingShape ring_for(const KGeom& g, int R) {
   if (g.bw == 8 && g.bh == 16) return ring_shape<8, 16>(g.p, R);
   return ring_shape<8, 8>(g.p, R);
 }
+
+static size_t ring_bytes(const RingShape& w) { return (size_t)w.s.rows * w.stride * 4; }
 
 #define ACBM_PRED_R_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8)
 
@@ -833,26 +839,33 @@ static int walkers_per_cu() {
   return n;
 }
 
+struct PredLaunch {
+  const PredArgs* jobs;
+  const uint32_t* order;
+  WsHeader* hdr;
+  uint32_t total_rows;
+  size_t lds;
+};
+
 template <int N, int M, int NT, bool HP = false>
-static int launch_pred_nmt(const PredArgs& a, int R, size_t lds,
-                           hipStream_t st) {
+static int launch_pred_nmt(const PredLaunch& L, int R, hipStream_t st) {
   switch (R) {
-#define ACBM_CASE(RR)                                                                      \
-  case RR: {                                                                               \
-    const void* fn = (const void*)k_predictive<N, M, RR, NT, HP>;                          \
-    if (lds > 64 * 1024)                                                                   \
-      (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
-    int per_cu = 0;                                                                        \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, lds) != hipSuccess || \
-        per_cu < 1)                                                                        \
-      per_cu = 1;                                                                          \
-    per_cu = std::min(per_cu, walkers_per_cu());                                           \
-    /* about as many row walkers as can be resident, never more than rows */              \
-    const int grid = (int)std::min<size_t>((size_t)device_cus() * per_cu,                  \
-                                           (size_t)a.npairs * a.g.by);                     \
-    ProfScope ps("predictive", st);                                                        \
-    hipLaunchKernelGGL((k_predictive<N, M, RR, NT, HP>), dim3(grid), dim3(NT), lds, st, a); \
-    break;                                                                                 \
+#define ACBM_CASE(RR)                                                                        \
+  case RR: {                                                                                 \
+    const void* fn = (const void*)k_predictive<N, M, RR, NT, HP>;                            \
+    if (L.lds > 64 * 1024)                                                                   \
+      (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds); \
+    int per_cu = 0;                                                                          \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, L.lds) != hipSuccess || \
+        per_cu < 1)                                                                          \
+      per_cu = 1;                                                                            \
+    per_cu = std::min(per_cu, walkers_per_cu());                                             \
+    /* about as many row walkers as can be resident, never more than rows */                \
+    const int grid = (int)std::min<size_t>((size_t)device_cus() * per_cu, L.total_rows);    \
+    ProfScope ps("predictive", st);                                                          \
+    hipLaunchKernelGGL((k_predictive<N, M, RR, NT, HP>), dim3(grid), dim3(NT), L.lds, st,    \
+                       L.jobs, L.order, L.hdr, L.total_rows);                                \
+    break;                                                                                   \
   }
     ACBM_PRED_R_LIST(ACBM_CASE)
 #undef ACBM_CASE
@@ -865,11 +878,11 @@ static int launch_pred_nmt(const PredArgs& a, int R, size_t lds,
 
 // Half-pel precision runs with 256-thread walkers only.
 template <int N, int M>
-static int launch_pred_nm(const PredArgs& a, int R, int nt, size_t lds, bool hp, hipStream_t st) {
-  if (hp) return launch_pred_nmt<N, M, 256, true>(a, R, lds, st);
-  if (nt == 128) return launch_pred_nmt<N, M, 128>(a, R, lds, st);
-  if (nt == 512) return launch_pred_nmt<N, M, 512>(a, R, lds, st);
-  return launch_pred_nmt<N, M, 256>(a, R, lds, st);
+static int launch_pred_nm(const PredLaunch& L, int R, int nt, bool hp, hipStream_t st) {
+  if (hp) return launch_pred_nmt<N, M, 256, true>(L, R, st);
+  if (nt == 128) return launch_pred_nmt<N, M, 128>(L, R, st);
+  if (nt == 512) return launch_pred_nmt<N, M, 512>(L, R, st);
+  return launch_pred_nmt<N, M, 256>(L, R, st);
 }
 
 // Threads per row walker (128, 256 or 512); ACBM_ROW_THREADS overrides.
@@ -892,15 +905,15 @@ static int row_threads() {
 // 5 7.4, 6 8.7, 8 11.2 ms).  A single pair (68 walkers, each alone on its
 // CU) is faster with the one-round R = 5 (2.0 against 2.6 ms).
 // ACBM_PRED_R overrides.
-static int pick_rows(const KGeom& g, int nt, uint32_t npairs) {
-  const bool shared_cus = (size_t)npairs * g.by > (size_t)device_cus();
+static int pick_rows(const KGeom& g, int nt, size_t total_rows) {
+  const bool shared_cus = total_rows > (size_t)device_cus();
   const char* force = std::getenv("ACBM_PRED_R");
   const int nc = g.bw / 4;
   int bestR = 0;
   long best = 0;
   for (int R : {1, 2, 3, 4, 5, 6, 8}) {
     const RingShape w = ring_for(g, R);
-    if ((size_t)w.s.rows * w.stride * 4 > (size_t)lds_limit()) continue;
+    if (ring_bytes(w) > (size_t)lds_limit()) continue;
     if (force && std::atoi(force) != R) continue;
     if (!force && shared_cus && g.bw == 16 && R > 3) continue;
     const long rounds = (w.s.quads * w.s.groups + nt - 1) / nt;
@@ -913,65 +926,98 @@ static int pick_rows(const KGeom& g, int nt, uint32_t npairs) {
   return bestR;
 }
 
+int plan_predictive_group(const KGeom* geoms, int n, bool hp, size_t total_rows,
+                          PredGroupPlan* pl) {
+  if (n < 1) return fail(ACBM_E_INVAL, "a predictive group needs a job");
+  int imax = 0;  // the largest window decides which row blockings fit in LDS
+  for (int i = 1; i < n; ++i)
+    if (geoms[i].p > geoms[imax].p) imax = i;
+  pl->threads = hp ? 256 : row_threads();
+  pl->R = pick_rows(geoms[imax], pl->threads, total_rows);
+  if (!pl->R) return fail(ACBM_E_UNSUPPORTED, "search window too large for the predictive kernel");
+  pl->lds = 0;
+  for (int i = 0; i < n; ++i) pl->lds = std::max(pl->lds, ring_bytes(ring_for(geoms[i], pl->R)));
+  return ACBM_OK;
+}
+
+PredArgs predictive_args(const KGeom& g, const acbm_params& prm, int algo, int R,
+                         uint32_t npairs) {
+  PredArgs a{};
+  a.g = g;
+  a.w = ring_for(g, R);
+  a.algo = algo;
+  a.lam = prm.lambda;
+  const unsigned __int128 t1 =
+      ((unsigned __int128)prm.alpha + (unsigned __int128)prm.beta * prm.qp * prm.qp) *
+      (unsigned __int128)(g.bw * g.bh);
+  a.c1_rhs = t1 > (unsigned __int128)UINT64_MAX ? UINT64_MAX : (uint64_t)t1;
+  a.gamma_num = prm.gamma_num;
+  a.gamma_den = prm.gamma_den;
+  a.npairs = (int)npairs;
+  a.row_levels = row_levels(g, (int)npairs);
+  return a;
+}
+
+int launch_predictive_group(int bw, int bh, bool hp, const PredGroupPlan& pl,
+                            const PredArgs* jobs, int njobs, uint32_t* order, WsHeader* hdr,
+                            uint32_t total_rows, hipStream_t st) {
+  if (njobs < 1 || njobs > kPredMaxJobs) return fail(ACBM_E_INVAL, "bad predictive group size");
+  if (!total_rows) return ACBM_OK;
+  {
+    ProfScope ps("setup", st);
+    hipLaunchKernelGGL(k_pred_setup, dim3(64, njobs), dim3(256), 0, st, jobs, njobs, order, hdr);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "launching the predictive setup");
+  const PredLaunch L{jobs, order, hdr, total_rows, pl.lds};
+  if (bw == 16 && bh == 16) return launch_pred_nm<16, 16>(L, pl.R, pl.threads, hp, st);
+  if (bw == 16 && bh == 8) return launch_pred_nm<16, 8>(L, pl.R, pl.threads, hp, st);
+  if (bw == 8 && bh == 16) return launch_pred_nm<8, 16>(L, pl.R, pl.threads, hp, st);
+  return launch_pred_nm<8, 8>(L, pl.R, pl.threads, hp, st);
+}
+
 int launch_predictive(const KGeom& g, const acbm_params& prm, int algo,
                       const uint8_t* const* frames, uint32_t npairs, const acbm_mv* prev_field,
                       void* ws, size_t ws_bytes, acbm_block_result* out, hipStream_t st) {
   if (ws_bytes < predictive_ws_bytes(g, npairs)) return fail(ACBM_E_NOMEM, "workspace too small");
   const bool hp = prm.subpel != 0;
-  const int nt = hp ? 256 : row_threads();
-  const int R = pick_rows(g, nt, std::min<uint32_t>(npairs, kMaxPairsPerLaunch));
-  if (!R) return fail(ACBM_E_UNSUPPORTED, "search window too large for the predictive kernel");
   const uint32_t per = std::min<uint32_t>(npairs, kMaxPairsPerLaunch);
+  PredGroupPlan pl;
+  int rc = plan_predictive_group(&g, 1, hp, (size_t)per * g.by, &pl);
+  if (rc) return rc;
   char* base = static_cast<char*>(ws);
+  size_t off = 0;
+  WsHeader* hdr = reinterpret_cast<WsHeader*>(base);
+  off += align256(sizeof(WsHeader));
+  uint32_t* order = reinterpret_cast<uint32_t*>(base + off);
+  off += align256((size_t)per * g.by * sizeof(uint32_t));
+  uint32_t* words = reinterpret_cast<uint32_t*>(base + off);
+  off += align256((size_t)per * g.nb * sizeof(uint32_t));
+  const uint8_t** fptr = reinterpret_cast<const uint8_t**>(base + off);
+  off += align256((size_t)(kMaxPairsPerLaunch + 1) * sizeof(void*));
+  PredArgs* table = reinterpret_cast<PredArgs*>(base + off);
   for (uint32_t p0 = 0; p0 < npairs; p0 += kMaxPairsPerLaunch) {
     const int n = (int)std::min<uint32_t>(kMaxPairsPerLaunch, npairs - p0);
-    PredArgs a{};
-    a.g = g;
-    a.algo = algo;
-    a.lam = prm.lambda;
-    const unsigned __int128 t1 =
-        ((unsigned __int128)prm.alpha + (unsigned __int128)prm.beta * prm.qp * prm.qp) *
-        (unsigned __int128)(g.bw * g.bh);
-    a.c1_rhs = t1 > (unsigned __int128)UINT64_MAX ? UINT64_MAX : (uint64_t)t1;
-    a.gamma_num = prm.gamma_num;
-    a.gamma_den = prm.gamma_den;
-    a.npairs = n;
-    a.row_levels = row_levels(g, n);
+    PredArgs a = predictive_args(g, prm, algo, pl.R, (uint32_t)n);
     if (p0 == 0) {
       a.prev0 = reinterpret_cast<const uint8_t*>(prev_field);
       a.prev0_stride = sizeof(acbm_mv);
-    } else {
+    } else {  // the previous launch's last pair
       a.prev0 = reinterpret_cast<const uint8_t*>(out + (size_t)(p0 - 1) * g.nb);
       a.prev0_stride = sizeof(acbm_block_result);
     }
-    a.hdr = reinterpret_cast<WsHeader*>(base);
-    a.row_order = reinterpret_cast<uint32_t*>(base + align256(sizeof(WsHeader)));
-    a.words = reinterpret_cast<uint32_t*>(base + align256(sizeof(WsHeader)) +
-                                          align256((size_t)per * g.by * sizeof(uint32_t)));
-    a.frames = reinterpret_cast<const uint8_t**>(
-        base + align256(sizeof(WsHeader)) + align256((size_t)per * g.by * sizeof(uint32_t)) +
-        align256((size_t)per * g.nb * sizeof(uint32_t)));
+    a.hdr = hdr;
+    a.words = words;
+    a.frames = fptr;
     a.out = out + (size_t)p0 * g.nb;
     FramePtrs fr{};
     for (int k = 0; k <= n; ++k) fr.f[k] = frames[p0 + k];
-
-    a.w = ring_for(g, R);
-    const size_t lds = (size_t)a.w.s.rows * a.w.stride * 4;
-
-    const int setup_grid = (int)std::min<size_t>(1024, ((size_t)n * g.nb + 255) / 256 + 1);
-    {
-      ProfScope ps("setup", st);
-      hipLaunchKernelGGL(k_pred_setup, dim3(setup_grid), dim3(256), 0, st, a, fr);
-    }
+    hipLaunchKernelGGL(k_pred_put_job, dim3(1), dim3(128), 0, st, a, fr, table, fptr);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "launching the predictive setup");
-
-    int rc;
-    if (g.bw == 16 && g.bh == 16) rc = launch_pred_nm<16, 16>(a, R, nt, lds, hp, st);
-    else if (g.bw == 16 && g.bh == 8) rc = launch_pred_nm<16, 8>(a, R, nt, lds, hp, st);
-    else if (g.bw == 8 && g.bh == 16) rc = launch_pred_nm<8, 16>(a, R, nt, lds, hp, st);
-    else rc = launch_pred_nm<8, 8>(a, R, nt, lds, hp, st);
-    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "writing the predictive job");
+    if ((rc = launch_predictive_group(g.bw, g.bh, hp, pl, table, 1, order, hdr,
+                                      (uint32_t)n * g.by, st)))
+      return rc;
   }
   return ACBM_OK;
 }

@@ -99,6 +99,30 @@ def test_batch_argument_errors():
     jobs = (acbm.Job * 1)(job)
     assert L.acbm_batch_workspace_size(jobs, 1, C.byref(n)) == acbm.OK and n.value > 0
     assert L.acbm_batch(jobs, 1, FAKE, 16, None) == acbm.E_NOMEM
+    st = C.c_int()
+    assert L.acbm_batch_status(jobs, 1, None, n.value, None, C.byref(st)) == acbm.E_INVAL
+    assert L.acbm_batch_status(jobs, 1, FAKE, n.value, None, None) == acbm.E_INVAL
+    assert L.acbm_batch_status(jobs, 1, FAKE, 16, None, C.byref(st)) == acbm.E_NOMEM
+
+
+def test_batch_workspace_grows_with_walker_groups():
+    """PBM/ACBM jobs of one block size and precision share one walker
+    group: the batch workspace holds every job's vector words plus one
+    header and row order per group, so adding a job of another block size
+    adds a header."""
+    L = acbm.lib()
+    ptrs = (C.c_void_p * 3)(FAKE, FAKE, FAKE)
+
+    def size(*shapes):
+        jobs = (acbm.Job * len(shapes))(*[
+            acbm.Job(_g(block_w=bw, block_h=bh), acbm.Params(lam=4).c(), acbm.ALGO_ACBM, 3, ptrs,
+                     FAKE) for bw, bh in shapes])
+        n = C.c_size_t()
+        assert L.acbm_batch_workspace_size(jobs, len(shapes), C.byref(n)) == acbm.OK
+        return n.value
+
+    one, two_same, two_diff = size((16, 16)), size((16, 16), (16, 16)), size((16, 16), (8, 8))
+    assert two_same > one and two_diff > two_same
 
 
 def test_default_params_scale_with_block_size():

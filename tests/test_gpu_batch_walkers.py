@@ -1,0 +1,126 @@
+"""Batched PBM/ACBM: the jobs of a batch with one block size and precision
+share one row-walker launch, their rows taken in level order across jobs.
+Every job's result equals the oracle's run of that sequence alone, bit for
+bit, for groups that mix p, frame size, frame count, algorithm and the
+ACBM thresholds, for a group split at its job limit, and on graph replays."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_0710_4819_amd import acbm, synth
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("mv_x", "mv_y", "sad", "j", "rate_bits", "cands", "mode", "intra_x")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def oparams(p: acbm.Params) -> oracle.Params:
+    return oracle.Params(lam=p.lam, qp=p.qp, alpha=p.alpha, beta=p.beta,
+                         gamma_num=p.gamma_num, gamma_den=p.gamma_den, subpel=p.subpel)
+
+
+def params(bw, bh, lam, subpel=0, qp=None, alpha=None):
+    p0 = acbm.default_params(bw, bh, lam, qp)
+    return acbm.Params(lam=p0.lam, qp=p0.qp, alpha=p0.alpha if alpha is None else alpha,
+                       beta=p0.beta, gamma_num=p0.gamma_num, gamma_den=p0.gamma_den,
+                       subpel=subpel)
+
+
+def assert_oracle(name, got, frames, bw, bh, p, prm, algo):
+    want = oracle.sequence(frames, bw, bh, p, oparams(prm), algo)
+    for f in FIELDS:
+        g, w = got[f].astype(np.int64), want[f].astype(np.int64)
+        if not np.array_equal(g, w):
+            bad = np.argwhere(g != w)[0]
+            raise AssertionError(f"{name}: field {f} differs at {tuple(bad)}: "
+                                 f"{g[tuple(bad)]} vs {w[tuple(bad)]}")
+
+
+def _walker_jobs():
+    """Sequences of uneven geometry and length for every block size, integer
+    and half-pel, PBM and ACBM (16 jobs in 8 groups)."""
+    sc = synth.cif_scene(nframes=6, lam=8)
+    hd = synth.hd_scene(nframes=3, lam=8)
+    jobs = []
+    for bw, bh in ((16, 16), (16, 8), (8, 16), (8, 8)):
+        for subpel in (0, 1):
+            jobs.append(([f[:144, :176] for f in sc.frames[:6]], bw, bh, 7, acbm.ALGO_ACBM,
+                         params(bw, bh, 8, subpel)))
+            jobs.append(([f[:96, :128] for f in hd.frames[:3]], bw, bh, 16 if subpel else 24,
+                         acbm.ALGO_PBM if bw == bh else acbm.ALGO_ACBM,
+                         params(bw, bh, 4, subpel, qp=12, alpha=400)))
+    return jobs
+
+
+def _batch(dev, jobs):
+    b = acbm.Batch(dev)
+    for frames, bw, bh, p, algo, prm in jobs:
+        b.add([torch.from_numpy(np.ascontiguousarray(f)).to(dev) for f in frames], bw, bh, p,
+              prm, algo)
+    return b
+
+
+def test_walker_groups_match_the_oracle():
+    dev = torch.device("cuda", 0)
+    jobs = _walker_jobs()
+    b = _batch(dev, jobs)
+    say(f"batch of {len(jobs)} PBM/ACBM jobs")
+    got = [acbm.to_numpy(o) for o in b.run()]
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    for i, (frames, bw, bh, p, algo, prm) in enumerate(jobs):
+        say(f"job {i}: {frames[0].shape} {bw}x{bh} p={p} algo={algo} subpel={prm.subpel}")
+        assert_oracle(f"job {i}", got[i], frames, bw, bh, p, prm, algo)
+
+
+def test_walker_group_graph_replays():
+    dev = torch.device("cuda", 0)
+    jobs = _walker_jobs()[:6]
+    b = _batch(dev, jobs)
+    eager = [acbm.to_numpy(o.clone()) for o in b.run()]
+    ws = torch.empty(max(256, b.workspace_size()), dtype=torch.uint8, device=dev)
+    gr = acbm.BatchGraph(b, ws)
+    try:
+        for rep in range(3):
+            for o in b.outs:
+                o.fill_(0xA5)
+            say(f"graph replay {rep}")
+            outs = gr.launch()
+            torch.cuda.synchronize()
+            for i, o in enumerate(outs):
+                assert np.array_equal(acbm.to_numpy(o), eager[i]), f"replay {rep}, job {i}"
+            x = torch.randn(1 << 18, device=dev)
+            _ = (x * 2).sum().item()
+    finally:
+        gr.close()
+    for i, (frames, bw, bh, p, algo, prm) in enumerate(jobs):
+        assert_oracle(f"job {i}", eager[i], frames, bw, bh, p, prm, algo)
+
+
+def test_walker_group_split_at_its_job_limit():
+    """More tiny jobs than one group holds: the second group gives the same
+    bit-exact results; every job also matches the oracle."""
+    dev = torch.device("cuda", 0)
+    g = synth.rng(77)
+    jobs = []
+    for s in range(300):
+        h, w = (32, 48) if s % 3 else (48, 64)
+        base = g.integers(0, 256, size=(h, w)).astype(np.uint8)
+        nfr = 2 + s % 3
+        frames = [np.roll(base, (k * (s % 5 - 2), k * (s % 7 - 3)), axis=(0, 1)) for k in range(nfr)]
+        frames = [np.clip(f.astype(np.int32) + g.integers(-3, 4, size=f.shape), 0, 255)
+                  .astype(np.uint8) for f in frames]
+        jobs.append((frames, 16, 16, 4 + s % 5, acbm.ALGO_ACBM if s % 2 else acbm.ALGO_PBM,
+                     params(16, 16, 4)))
+    b = _batch(dev, jobs)
+    say(f"batch of {len(jobs)} tiny jobs")
+    got = [acbm.to_numpy(o) for o in b.run()]
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    for i, (frames, bw, bh, p, algo, prm) in enumerate(jobs):
+        assert_oracle(f"job {i}", got[i], frames, bw, bh, p, prm, algo)
