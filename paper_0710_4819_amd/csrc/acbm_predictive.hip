@@ -895,16 +895,18 @@ static int row_threads() {
   return nt;
 }
 
-// Row blocking R of the critical search: the least issue time per lane,
-// rounds * (QSAD cycles of a task + its loads and pricing), among the R
-// whose ring fits in LDS.  When a launch has more block rows than the
-// device has CUs, walkers share CUs and, for 16-wide blocks, R stays <= 3:
-// under the register budget of 3 waves per SIMD the R >= 4 kernels sit at
-// 165-168 VGPRs and spill for R = 4, 6 and 8; on the 1920x1088 p = 32 ACBM
-// sequence (59 pairs) R = 3 was fastest (6.9 ms; R = 1 7.3, 2 8.1, 4 10.5,
-// 5 7.4, 6 8.7, 8 11.2 ms).  A single pair (68 walkers, each alone on its
-// CU) is faster with the one-round R = 5 (2.0 against 2.6 ms).
-// ACBM_PRED_R overrides.
+// Row blocking R of the critical search.  When a launch has more block rows
+// than the device has CUs, walkers share CUs and the launch is bound by how
+// many rows are in flight: R = 1, whose walkers need the fewest registers
+// (so the most fit on a CU), was fastest everywhere it was measured.  On the
+// 1920x1088 16x16 p = 32 ACBM sequence (59 pairs): R = 1 6.9 ms, 2 7.3,
+// 4 10.9, 5 7.3 ms.  On the 64-sequence batch, its 8x8 group (28
+// sequences): R = 1 11.8 ms, 2 13.0, 3 14.6, 4 18.4, 5 20.2, 6 21.4 ms; its
+// 16x16 group: R = 1 5.0 ms, 3 5.2 ms.  Otherwise each walker has its CU to
+// itself and the critical search's latency matters: the least issue time
+// per lane, rounds * (QSAD cycles of a task + its loads and pricing), among
+// the R whose ring fits in LDS (a single HD pair: R = 5, 2.0 ms against 2.6
+// ms with R = 3).  ACBM_PRED_R overrides.
 static int pick_rows(const KGeom& g, int nt, size_t total_rows) {
   const bool shared_cus = total_rows > (size_t)device_cus();
   const char* force = std::getenv("ACBM_PRED_R");
@@ -915,7 +917,7 @@ static int pick_rows(const KGeom& g, int nt, size_t total_rows) {
     const RingShape w = ring_for(g, R);
     if (ring_bytes(w) > (size_t)lds_limit()) continue;
     if (force && std::atoi(force) != R) continue;
-    if (!force && shared_cus && g.bw == 16 && R > 3) continue;
+    if (!force && shared_cus && R > 1) continue;
     const long rounds = (w.s.quads * w.s.groups + nt - 1) / nt;
     const long cost = rounds * ((long)R * g.bh * nc * 16 + 8L * (R + g.bh - 1) + 160L * R);
     if (!bestR || cost < best) {
