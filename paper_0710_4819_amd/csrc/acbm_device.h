@@ -7,6 +7,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "acbm_internal.h"
@@ -24,6 +25,23 @@ __device__ __forceinline__ T ld_global(const void* p) {
 template <typename T>
 __device__ __forceinline__ void st_global(void* p, const T& v) {
   *(__attribute__((address_space(1))) T*)p = v;
+}
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ u32x4 ld_global_x4(const void* p) {
+  return *(const __attribute__((address_space(1))) u32x4*)p;
+}
+
+// One block's result as two 16-byte global stores: mv (x in the low, y in
+// the high half), sad, j, rate_bits | cands, mode, intra_x (u64 at byte 24).
+static_assert(sizeof(acbm_block_result) == 32, "result layout");
+static_assert(offsetof(acbm_block_result, intra_x) == 24, "result layout");
+__device__ __forceinline__ void put_result(acbm_block_result* out, int u, int v, uint32_t sad,
+                                           uint32_t j, uint32_t rate, uint32_t cands,
+                                           uint32_t mode, uint32_t intra) {
+  typedef __attribute__((address_space(1))) u32x4 gu32x4;
+  gu32x4* o = (gu32x4*)out;
+  o[0] = u32x4{((uint32_t)v << 16) | ((uint32_t)u & 0xFFFFu), sad, j, rate};
+  o[1] = u32x4{cands, mode, intra, 0u};
 }
 
 // ---------------------------------------------------------------------------

@@ -456,16 +456,9 @@ __device__ __forceinline__ void half_finish(const KGeom& g, int b, int U0, int V
   const uint32_t j = (uint32_t)(best >> 32), sad = j - lam * rate;
   if (writer) {
     const int r = b / g.bx, c = b - r * g.bx;
-    acbm_block_result res;
-    res.mv.x = (int16_t)U;
-    res.mv.y = (int16_t)V;
-    res.sad = sad;
-    res.j = j;
-    res.rate_bits = rate;
-    res.cands = valid_count(p, c * g.bw, r * g.bh, g.bw, g.bh, g.width, g.height) + nh;
-    res.mode = ACBM_MODE_FSBM;
-    res.intra_x = intra_x;
-    *out = res;
+    put_result(out, U, V, sad, j, rate,
+               valid_count(p, c * g.bw, r * g.bh, g.bw, g.bh, g.width, g.height) + nh,
+               ACBM_MODE_FSBM, intra_x);
     *st = (sad << 16) | pack_mv(U, V);
   }
 }
@@ -559,27 +552,45 @@ __device__ __forceinline__ void half_decide_lane(const KGeom& g, const HalfRec& 
 // Half-pel resolve of one frame pair by the whole group.  Every block needs
 // its predictor (the half-pel step is priced with it), so the blocks are
 // decided in anti-diagonal order: step k holds the blocks (r, k - 2r), whose
-// left, top and top-right neighbours all belong to earlier steps.  The
-// blocks of a step are dealt round-robin over the waves (block i of the step
-// to wave i % nwaves, lane i / nwaves; a step has at most `by` blocks, which
-// the host keeps <= the group size); a block with a single possible winner
-// is decided by its own lane, the others by their whole wave.  Records do
-// not depend on any decision, so each thread loads its block of the next
-// step while the current step runs.
+// left, top and top-right neighbours all belong to earlier steps.  Thread i
+// takes block i of every step (a step has at most `by` <= 1024 blocks, the
+// group size), so a step's blocks fill the first waves and the rest skip the
+// lane work.  A block with few possible winners is decided by its own lane;
+// the others go to a list in LDS and, after a barrier, are decided by whole
+// waves, one block per wave at a time.  Records do not depend on any
+// decision, so each thread loads its block of the next step while the
+// current step runs.
 __device__ __forceinline__ int step_block(const KGeom& g, int k, int i) {
   const int r_lo = max(0, (k - (g.bx - 1) + 1) / 2), r_hi = min(g.by - 1, k / 2);
   const int r = r_lo + i;
   return r <= r_hi ? r * g.bx + (k - 2 * r) : -1;
 }
 
+// The blocks of the current step left to whole waves: block index and
+// number of possible winners, and the list length of two consecutive steps
+// (step k appends to cnt[k & 1] and clears cnt[(k + 1) & 1] for the next).
+struct MultiList {
+  uint32_t b[1024];
+  uint32_t n[1024];
+  int cnt[2];
+};
+__device__ __forceinline__ MultiList& multi_list() {
+  __shared__ MultiList m;
+  return m;
+}
+
 __device__ __forceinline__ void load_half_rec(const BlockRec* __restrict__ recs, int b,
                                               HalfRec& h) {
-  if (b < 0) return;
-  const BlockRec* rec = recs + b;
-  h.count = rec->count;
-#pragma unroll
-  for (int q = 0; q < 5; ++q) h.e[q] = rec->e[q];
-  h.intra_x = rec->intra_x;
+  if (b < 0) return;  // global loads (see ld_global): only LDS waits follow
+  const u32x4 a = ld_global_x4(recs + b);                          // sad_min, count, intra_x
+  const u32x4 e = ld_global_x4(reinterpret_cast<const char*>(recs + b) + 16);  // e[0..3]
+  h.count = a.y;
+  h.intra_x = a.z;
+  h.e[0] = e.x;
+  h.e[1] = e.y;
+  h.e[2] = e.z;
+  h.e[3] = e.w;
+  h.e[4] = ld_global<uint32_t>(&recs[b].e[4]);
 }
 
 __device__ __forceinline__ void resolve_pair_half(const KGeom& g,
@@ -592,31 +603,39 @@ __device__ __forceinline__ void resolve_pair_half(const KGeom& g,
   const int p = g.p, bx = g.bx, by = g.by;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int steps = (bx - 1) + 2 * (by - 1) + 1;
-  const int i = lane * nwaves + wave;  // this thread's place in every step
+  const int i = threadIdx.x;  // this thread's place in every step
+  MultiList& ml = multi_list();
+  if (threadIdx.x < 2) ml.cnt[threadIdx.x] = 0;
+  __syncthreads();
   HalfRec h{}, hn{};
   int b = step_block(g, 0, i);
   load_half_rec(recs, b, h);
   for (int k = 0; k < steps; ++k) {
     const int bn = step_block(g, k + 1, i);
     load_half_rec(recs, bn, hn);  // in flight while this step is decided
-    {
-      const int r = b >= 0 ? b / bx : 0, c = b >= 0 ? b - r * bx : 0;
+    // the next step's list: its last readers passed a barrier since
+    if (threadIdx.x == 0) ml.cnt[(k + 1) & 1] = 0;
+    if (b >= 0) {
+      const int r = b / bx, c = b - r * bx;
       int px = 0, py = 0;
-      bool multi = false;
-      if (b >= 0) {
-        median_pred(st, b, r, c, bx, &px, &py);  // its neighbours are decided
-        if (h.count == 1)
-          half_decide_lane(g, h, b, px, py, lam, out + b, st + b);
-        else
-          multi = true;
+      median_pred(st, b, r, c, bx, &px, &py);  // its neighbours are decided
+      if (h.count == 1) {
+        half_decide_lane(g, h, b, px, py, lam, out + b, st + b);
+      } else {
+        const int q = atomicAdd(&ml.cnt[k & 1], 1);
+        ml.b[q] = (uint32_t)b;
+        ml.n[q] = h.count;
       }
-      uint64_t mask = __ballot(multi);
-      while (mask) {
-        const int q = __ffsll((unsigned long long)mask) - 1;
-        mask &= mask - 1;
-        const int bb = __shfl(b, q, 64);
-        const int qx = __shfl(px, q, 64), qy = __shfl(py, q, 64);
-        const uint32_t cnt = (uint32_t)__shfl((int)h.count, q, 64);
+    }
+    __syncthreads();  // lane decisions and the list
+    const int nm = __builtin_amdgcn_readfirstlane(ml.cnt[k & 1]);
+    if (nm) {
+      for (int j = wave; j < nm; j += nwaves) {
+        const int bb = (int)ml.b[j];
+        const uint32_t cnt = ml.n[j];
+        const int r = bb / bx, c = bb - r * bx;
+        int qx = 0, qy = 0;
+        median_pred(st, bb, r, c, bx, &qx, &qy);
         const uint16_t* row = ovf + (size_t)bb * ovf_stride(p);
         if (cnt <= half_cap(p)) {
           half_decide_prepared(g, recs + bb, row, cnt, bb, qx, qy, lam, out + bb, st + bb);
@@ -625,8 +644,8 @@ __device__ __forceinline__ void resolve_pair_half(const KGeom& g,
           half_decide(g, recs + bb, cur, ref, bb, qx, qy, lam, key, out + bb, st + bb);
         }
       }
+      __syncthreads();  // this step's decisions before the next step reads them
     }
-    __syncthreads();  // this step's decisions before the next step reads them
     b = bn;
     h = hn;
   }
@@ -646,11 +665,15 @@ static_assert(kShort == 28, "the record's list is 7 x 16 bytes");
 
 __device__ __forceinline__ void load_int_rec(const BlockRec* __restrict__ recs, int b,
                                              IntRec& r) {
-  if (b < 0) return;
-  const uint4* q = reinterpret_cast<const uint4*>(recs + b);
-  r.h = q[0];
+  if (b < 0) return;  // global loads (see ld_global): only LDS waits follow
+  const char* q = reinterpret_cast<const char*>(recs + b);
+  const u32x4 h = ld_global_x4(q);
+  r.h = make_uint4(h.x, h.y, h.z, h.w);
 #pragma unroll
-  for (int k = 0; k < 7; ++k) r.e[k] = q[1 + k];
+  for (int k = 0; k < 7; ++k) {
+    const u32x4 e = ld_global_x4(q + 16 * (1 + k));
+    r.e[k] = make_uint4(e.x, e.y, e.z, e.w);
+  }
 }
 
 // The decided block's result and decision word.
@@ -659,16 +682,9 @@ __device__ __forceinline__ void int_write(const KGeom& g, int b, int u, int v, u
                                           acbm_block_result* __restrict__ out, uint32_t* st) {
   const int r = b / g.bx, c = b - r * g.bx;
   const uint32_t rate = se_bits(u - px) + se_bits(v - py);
-  acbm_block_result res;
-  res.mv.x = (int16_t)u;
-  res.mv.y = (int16_t)v;
-  res.sad = sad;
-  res.j = sad + lam * rate;
-  res.rate_bits = rate;
-  res.cands = valid_count(g.p, c * g.bw, r * g.bh, g.bw, g.bh, g.width, g.height);
-  res.mode = ACBM_MODE_FSBM;
-  res.intra_x = intra_x;
-  *out = res;
+  put_result(out, u, v, sad, sad + lam * rate,
+             rate, valid_count(g.p, c * g.bw, r * g.bh, g.bw, g.bh, g.width, g.height),
+             ACBM_MODE_FSBM, intra_x);
   *st = (sad << 16) | pack_mv(u, v);
 }
 
@@ -711,31 +727,39 @@ __device__ __forceinline__ void resolve_pair_int(const KGeom& g,
   const int p = g.p, bx = g.bx, by = g.by;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int steps = (bx - 1) + 2 * (by - 1) + 1;
-  const int i = lane * nwaves + wave;  // this thread's place in every step
+  const int i = threadIdx.x;  // this thread's place in every step
+  MultiList& ml = multi_list();
+  if (threadIdx.x < 2) ml.cnt[threadIdx.x] = 0;
+  __syncthreads();
   IntRec h{}, hn{};
   int b = step_block(g, 0, i);
   load_int_rec(recs, b, h);
   for (int k = 0; k < steps; ++k) {
     const int bn = step_block(g, k + 1, i);
     load_int_rec(recs, bn, hn);  // in flight while this step is decided
-    {
-      const int r = b >= 0 ? b / bx : 0, c = b >= 0 ? b - r * bx : 0;
+    // the next step's list: its last readers passed a barrier since
+    if (threadIdx.x == 0) ml.cnt[(k + 1) & 1] = 0;
+    if (b >= 0) {
+      const int r = b / bx, c = b - r * bx;
       int px = 0, py = 0;
-      bool multi = false;
-      if (b >= 0) {
-        median_pred(st, b, r, c, bx, &px, &py);  // its neighbours are decided
-        if (h.h.y <= (uint32_t)kShort)
-          int_decide_lane(g, h, b, px, py, lam, out + b, st + b);
-        else
-          multi = true;
+      median_pred(st, b, r, c, bx, &px, &py);  // its neighbours are decided
+      if (h.h.y <= (uint32_t)kShort) {
+        int_decide_lane(g, h, b, px, py, lam, out + b, st + b);
+      } else {
+        const int q = atomicAdd(&ml.cnt[k & 1], 1);
+        ml.b[q] = (uint32_t)b;
+        ml.n[q] = h.h.z;  // intra_x, for the result
       }
-      uint64_t mask = __ballot(multi);
-      while (mask) {
-        const int q = __ffsll((unsigned long long)mask) - 1;
-        mask &= mask - 1;
-        const int bb = __shfl(b, q, 64);
-        const int qx = __shfl(px, q, 64), qy = __shfl(py, q, 64);
-        const uint32_t ix = (uint32_t)__shfl((int)h.h.z, q, 64);
+    }
+    __syncthreads();  // lane decisions and the list
+    const int nm = __builtin_amdgcn_readfirstlane(ml.cnt[k & 1]);
+    if (nm) {
+      for (int j = wave; j < nm; j += nwaves) {
+        const int bb = (int)ml.b[j];
+        const uint32_t ix = ml.n[j];
+        const int r = bb / bx, c = bb - r * bx;
+        int qx = 0, qy = 0;
+        median_pred(st, bb, r, c, bx, &qx, &qy);
         const uint64_t key =
             wave_block_argmin<false>(recs + bb, ovf + (size_t)bb * ovf_stride(p), p, qx, qy, lam);
         int u = 0, v = 0;
@@ -743,8 +767,8 @@ __device__ __forceinline__ void resolve_pair_int(const KGeom& g,
         const uint32_t sad = (uint32_t)(key >> 32) - lam * (se_bits(u - qx) + se_bits(v - qy));
         if (lane == 0) int_write(g, bb, u, v, sad, qx, qy, lam, ix, out + bb, st + bb);
       }
+      __syncthreads();  // this step's decisions before the next step reads them
     }
-    __syncthreads();  // this step's decisions before the next step reads them
     b = bn;
     h = hn;
   }
@@ -864,10 +888,18 @@ k_resolve(const KGeom g, const BlockRec* __restrict__ recs, const uint16_t* __re
   extern __shared__ uint32_t st_lds[];
   __shared__ int shared[2];
   const int pair = blockIdx.x;
-  resolve_pair<HP>(g, recs + (size_t)pair * g.nb, ovf + (size_t)pair * g.nb * ovf_stride(g.p),
-                   out + (size_t)pair * g.nb, lam,
-                   st_global ? st_global + (size_t)pair * g.nb : st_lds, shared,
-                   HP ? fr.f[pair + 1] : nullptr, HP ? fr.f[pair] : nullptr);
+  const BlockRec* r = recs + (size_t)pair * g.nb;
+  const uint16_t* o = ovf + (size_t)pair * g.nb * ovf_stride(g.p);
+  acbm_block_result* res = out + (size_t)pair * g.nb;
+  const uint8_t* cur = HP ? fr.f[pair + 1] : nullptr;
+  const uint8_t* ref = HP ? fr.f[pair] : nullptr;
+  // two call sites, so that each sees one memory kind for the state (a
+  // pointer that may be either compiles to FLAT accesses, whose waits also
+  // cover the record prefetch)
+  if (st_global)
+    resolve_pair<HP>(g, r, o, res, lam, st_global + (size_t)pair * g.nb, shared, cur, ref);
+  else
+    resolve_pair<HP>(g, r, o, res, lam, st_lds, shared, cur, ref);
 }
 
 // Half-pel SADs prepared off the resolve's sequential path.  For every block
@@ -982,11 +1014,22 @@ k_resolve_batch(const BatchJob* __restrict__ jobs, int njobs) {
   const BlockRec* recs = J.recs + (size_t)pair * g.nb;
   const uint16_t* ovf = J.ovf + (size_t)pair * g.nb * ovf_stride(g.p);
   acbm_block_result* out = J.out + (size_t)pair * g.nb;
-  uint32_t* st = J.mv_ws ? J.mv_ws + (size_t)pair * g.nb : st_lds;
-  if (__builtin_amdgcn_readfirstlane(J.subpel))
-    resolve_pair<true>(g, recs, ovf, out, J.lam, st, shared, J.frames[pair + 1], J.frames[pair]);
-  else
-    resolve_pair<false>(g, recs, ovf, out, J.lam, st, shared, nullptr, nullptr);
+  const bool hp = __builtin_amdgcn_readfirstlane(J.subpel) != 0;
+  const uint8_t* cur = hp ? ld_global<const uint8_t*>(J.frames + pair + 1) : nullptr;
+  const uint8_t* ref = hp ? ld_global<const uint8_t*>(J.frames + pair) : nullptr;
+  // one call site per memory kind of the state (see k_resolve)
+  if (__builtin_amdgcn_readfirstlane(J.mv_ws != nullptr)) {
+    uint32_t* st = J.mv_ws + (size_t)pair * g.nb;
+    if (hp)
+      resolve_pair<true>(g, recs, ovf, out, J.lam, st, shared, cur, ref);
+    else
+      resolve_pair<false>(g, recs, ovf, out, J.lam, st, shared, nullptr, nullptr);
+  } else {
+    if (hp)
+      resolve_pair<true>(g, recs, ovf, out, J.lam, st_lds, shared, cur, ref);
+    else
+      resolve_pair<false>(g, recs, ovf, out, J.lam, st_lds, shared, nullptr, nullptr);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -469,13 +469,7 @@ __device__ __forceinline__ uint64_t critical_search(const uint32_t* __restrict__
 __device__ __forceinline__ void write_result(acbm_block_result* out, uint32_t* word, int u, int v,
                                              uint32_t j, uint32_t rate, uint32_t lam,
                                              uint32_t cands, uint32_t mode, uint32_t intra) {
-  // acbm_block_result as two 16-byte stores: mv (x low, y high), sad, j,
-  // rate_bits | cands, mode, intra_x (u64 at byte 24)
-  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-  typedef __attribute__((address_space(1))) u32x4 gu32x4;
-  gu32x4* o = (gu32x4*)out;
-  o[0] = u32x4{((uint32_t)v << 16) | ((uint32_t)u & 0xFFFFu), j - lam * rate, j, rate};
-  o[1] = u32x4{cands, mode, intra, 0u};
+  put_result(out, u, v, j - lam * rate, j, rate, cands, mode, intra);
   store_word(word, kReady | pack_mv(u, v));
 }
 
