@@ -225,6 +225,29 @@ def test_full_size_hd_sampled(algo):
                 assert int(one[f]) == int(got[t][r, c][f]), (t, r, c, f, one, got[t][r, c])
 
 
+@pytest.mark.parametrize("subpel", [0, 1])
+def test_full_size_8x8_steps_sampled(subpel):
+    """1920x1088, 8x8 blocks, p = 16, lambda = 8 (a batch-mix sequence): most
+    blocks have several possible winners, so the FSBM resolve walks the 510
+    anti-diagonal steps with up to 120 blocks each, over two waves, and hands
+    the blocks with more than 28 winners to other waves.  40 blocks are
+    recomputed by the oracle from the GPU's own neighbouring vectors."""
+    w = synth.batch_sequence(19, nframes=2)
+    assert (w.width, w.height, w.block_w, w.p) == (1920, 1088, 8, 16)
+    p0 = acbm.default_params(8, 8, 8)
+    prm = acbm.Params(lam=p0.lam, qp=p0.qp, alpha=p0.alpha, beta=p0.beta,
+                      gamma_num=p0.gamma_num, gamma_den=p0.gamma_den, subpel=subpel)
+    cur, ref = w.frames[1], w.frames[0]
+    say(f"1080p 8x8 p=16 subpel={subpel}")
+    got = acbm.to_numpy(acbm.fsbm_frame(dev(cur), dev(ref), 8, 8, 16, prm))
+    assert np.array_equal(got["intra_x"].astype(np.uint64), oracle.intra_table(cur, 8, 8))
+    for (r, c) in _sample_blocks(*got.shape, 40, 300 + subpel):
+        one = oracle.block(cur, ref, 8, 8, 16, oparams(prm), acbm.ALGO_FSBM, got["mv_x"],
+                           got["mv_y"], r, c)
+        for f in FIELDS:
+            assert int(one[f]) == int(got[r, c][f]), (r, c, f, one, got[r, c])
+
+
 def test_deterministic_repeat():
     sc = synth.cif_scene(nframes=4, lam=8)
     prm = acbm.default_params(16, 16, 8)
