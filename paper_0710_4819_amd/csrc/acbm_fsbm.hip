@@ -579,6 +579,17 @@ __device__ __forceinline__ MultiList& multi_list() {
   return m;
 }
 
+// Brings the record of this thread's block two steps ahead into the caches:
+// the full prefetch of the next step then hits.  (The step loop waits for its
+// prefetch at the end of each step, so that prefetch alone covers one step.)
+// The word is only used one step later, after that wait, so the load adds
+// no wait of its own.
+__device__ __forceinline__ uint32_t touch_rec(const BlockRec* __restrict__ recs, int b) {
+  return b >= 0 ? ld_global<uint32_t>(&recs[b].count) : 0u;
+}
+// Consumes the touched words so that the loads stay; emits no instruction.
+__device__ __forceinline__ void keep(uint32_t v) { __asm__ volatile("" ::"v"(v)); }
+
 __device__ __forceinline__ void load_half_rec(const BlockRec* __restrict__ recs, int b,
                                               HalfRec& h) {
   if (b < 0) return;  // global loads (see ld_global): only LDS waits follow
@@ -608,11 +619,14 @@ __device__ __forceinline__ void resolve_pair_half(const KGeom& g,
   if (threadIdx.x < 2) ml.cnt[threadIdx.x] = 0;
   __syncthreads();
   HalfRec h{}, hn{};
+  uint32_t sink = 0, touched = 0;
   int b = step_block(g, 0, i);
   load_half_rec(recs, b, h);
   for (int k = 0; k < steps; ++k) {
     const int bn = step_block(g, k + 1, i);
     load_half_rec(recs, bn, hn);  // in flight while this step is decided
+    sink ^= touched;  // last step's word, waited for with the prefetch
+    touched = touch_rec(recs, step_block(g, k + 2, i));
     // the next step's list: its last readers passed a barrier since
     if (threadIdx.x == 0) ml.cnt[(k + 1) & 1] = 0;
     if (b >= 0) {
@@ -649,6 +663,7 @@ __device__ __forceinline__ void resolve_pair_half(const KGeom& g,
     b = bn;
     h = hn;
   }
+  keep(sink ^ touched);
 }
 
 // Integer resolve: the same anti-diagonal order as the half-pel one.  Each
@@ -732,11 +747,14 @@ __device__ __forceinline__ void resolve_pair_int(const KGeom& g,
   if (threadIdx.x < 2) ml.cnt[threadIdx.x] = 0;
   __syncthreads();
   IntRec h{}, hn{};
+  uint32_t sink = 0, touched = 0;
   int b = step_block(g, 0, i);
   load_int_rec(recs, b, h);
   for (int k = 0; k < steps; ++k) {
     const int bn = step_block(g, k + 1, i);
     load_int_rec(recs, bn, hn);  // in flight while this step is decided
+    sink ^= touched;  // last step's word, waited for with the prefetch
+    touched = touch_rec(recs, step_block(g, k + 2, i));
     // the next step's list: its last readers passed a barrier since
     if (threadIdx.x == 0) ml.cnt[(k + 1) & 1] = 0;
     if (b >= 0) {
@@ -772,6 +790,7 @@ __device__ __forceinline__ void resolve_pair_int(const KGeom& g,
     b = bn;
     h = hn;
   }
+  keep(sink ^ touched);
 }
 
 // Integer resolve when few blocks have several possible winners: blocks
