@@ -793,6 +793,123 @@ __device__ __forceinline__ void resolve_pair_int(const KGeom& g,
   keep(sink ^ touched);
 }
 
+// The same schedule with four lanes per block, for frames of at most 256
+// block rows (a step then fits in a quarter of the group).  Lane q of a
+// block's quad prefetches 32 bytes of its record for the next step: the
+// header and e[0..3] for q = 0, e[8q-4 .. 8q+3] otherwise.  Each lane prices
+// the listed winners it holds and a quad minimum gives the block's key, so
+// the serial pricing of up to 28 winners becomes at most 8 per lane.
+struct IntPart {
+  u32x4 a, b;
+};
+
+__device__ __forceinline__ void load_int_part(const BlockRec* __restrict__ recs, int b, int q,
+                                              IntPart& r) {
+  if (b < 0) return;
+  const char* base = reinterpret_cast<const char*>(recs + b) + 32 * q;
+  r.a = ld_global_x4(base);
+  r.b = ld_global_x4(base + 16);
+}
+
+// Lane 0's value to the four lanes of its quad (DPP quad_perm 0,0,0,0).
+__device__ __forceinline__ uint32_t quad_bcast0(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x00, 0xF, 0xF, false);
+}
+
+// Minimum over the four lanes of a quad (quad_perm 1,0,3,2 then 2,3,0,1).
+__device__ __forceinline__ uint64_t quad_min_u64(uint64_t k) {
+  uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)k, 0xB1, 0xF, 0xF, false);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(k >> 32), 0xB1, 0xF, 0xF, false);
+  uint64_t o = ((uint64_t)hi << 32) | lo;
+  k = o < k ? o : k;
+  lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)k, 0x4E, 0xF, 0xF, false);
+  hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(k >> 32), 0x4E, 0xF, 0xF, false);
+  o = ((uint64_t)hi << 32) | lo;
+  return o < k ? o : k;
+}
+
+__device__ __forceinline__ void resolve_pair_int4(const KGeom& g,
+                                                  const BlockRec* __restrict__ recs,
+                                                  const uint16_t* __restrict__ ovf,
+                                                  acbm_block_result* __restrict__ out,
+                                                  uint32_t lam, uint32_t* st) {
+  const int p = g.p, bx = g.bx, by = g.by;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int steps = (bx - 1) + 2 * (by - 1) + 1;
+  const int i = (int)threadIdx.x >> 2, q = (int)threadIdx.x & 3;  // block slot, quarter
+  const uint32_t W = 2u * (uint32_t)p + 1u;
+  const uint32_t inv = (uint32_t)(((1ull << 32) + W - 1) / W);  // ras / W = umulhi(ras, inv)
+  const int s0 = q ? 8 * q - 4 : 0, nq = q ? 8 : 4;              // the entries this lane holds
+  MultiList& ml = multi_list();
+  if (threadIdx.x < 2) ml.cnt[threadIdx.x] = 0;
+  __syncthreads();
+  IntPart h{}, hn{};
+  uint32_t sink = 0, touched = 0;
+  int b = step_block(g, 0, i);
+  load_int_part(recs, b, q, h);
+  for (int k = 0; k < steps; ++k) {
+    const int bn = step_block(g, k + 1, i);
+    load_int_part(recs, bn, q, hn);  // in flight while this step is decided
+    sink ^= touched;                 // last step's word, waited for with the prefetch
+    touched = q == 0 ? touch_rec(recs, step_block(g, k + 2, i)) : 0u;
+    if (threadIdx.x == 0) ml.cnt[(k + 1) & 1] = 0;
+    const uint32_t count = quad_bcast0(h.a.y);  // the four lanes of a quad agree on b
+    if (b >= 0) {
+      const int r = b / bx, c = b - r * bx;
+      int px = 0, py = 0;
+      median_pred(st, b, r, c, bx, &px, &py);  // its neighbours are decided
+      if (count <= (uint32_t)kShort) {
+        const uint32_t e[8] = {q ? h.a.x : h.b.x, q ? h.a.y : h.b.y, q ? h.a.z : h.b.z,
+                               q ? h.a.w : h.b.w, h.b.x, h.b.y, h.b.z, h.b.w};
+        uint64_t best = ~0ull;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          if (s < nq && (uint32_t)(s0 + s) < count) {
+            const uint32_t ras = e[s] & 0xFFFFu;
+            const uint32_t vq = __umulhi(ras, inv);
+            const int v = (int)vq - p, u = (int)(ras - vq * W) - p;
+            const uint64_t kk = int_key<false>(e[s] >> 16, u, v, p, px, py, lam);
+            best = kk < best ? kk : best;
+          }
+        }
+        best = quad_min_u64(best);
+        if (q == 0) {
+          const uint32_t ras = (uint32_t)(best & 0xFFFFu);
+          const uint32_t vq = __umulhi(ras, inv);
+          const int v = (int)vq - p, u = (int)(ras - vq * W) - p;
+          const uint32_t sad = (uint32_t)(best >> 32) - lam * (se_bits(u - px) + se_bits(v - py));
+          int_write(g, b, u, v, sad, px, py, lam, h.a.z, out + b, st + b);
+        }
+      } else if (q == 0) {
+        const int at = atomicAdd(&ml.cnt[k & 1], 1);
+        ml.b[at] = (uint32_t)b;
+        ml.n[at] = h.a.z;  // intra_x, for the result
+      }
+    }
+    __syncthreads();  // lane decisions and the list
+    const int nm = __builtin_amdgcn_readfirstlane(ml.cnt[k & 1]);
+    if (nm) {
+      for (int j = wave; j < nm; j += nwaves) {
+        const int bb = (int)ml.b[j];
+        const uint32_t ix = ml.n[j];
+        const int r = bb / bx, c = bb - r * bx;
+        int qx = 0, qy = 0;
+        median_pred(st, bb, r, c, bx, &qx, &qy);
+        const uint64_t key =
+            wave_block_argmin<false>(recs + bb, ovf + (size_t)bb * ovf_stride(p), p, qx, qy, lam);
+        int u = 0, v = 0;
+        window_uv((uint32_t)(key & 0xFFFFu), p, &u, &v);
+        const uint32_t sad = (uint32_t)(key >> 32) - lam * (se_bits(u - qx) + se_bits(v - qy));
+        if (lane == 0) int_write(g, bb, u, v, sad, qx, qy, lam, ix, out + bb, st + bb);
+      }
+      __syncthreads();  // this step's decisions before the next step reads them
+    }
+    b = bn;
+    h = hn;
+  }
+  keep(sink ^ touched);
+}
+
 // Integer resolve when few blocks have several possible winners: blocks
 // with a single one are decided at once, in parallel, without a predictor;
 // the rest are decided in sweeps as soon as their left, top and top-right
@@ -891,6 +1008,8 @@ __device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __r
     const int nmulti = __builtin_amdgcn_readfirstlane(shared[1]);
     if (4 * nmulti < g.nb)
       resolve_pair_sweeps(g, recs, ovf, out, lam, st, shared);
+    else if (4 * g.by <= (int)blockDim.x)
+      resolve_pair_int4(g, recs, ovf, out, lam, st);
     else
       resolve_pair_int(g, recs, ovf, out, lam, st);
   }
