@@ -666,6 +666,130 @@ __device__ __forceinline__ void resolve_pair_half(const KGeom& g,
   keep(sink ^ touched);
 }
 
+// Lane 0's value to the four lanes of its quad (DPP quad_perm 0,0,0,0).
+__device__ __forceinline__ uint32_t quad_bcast0(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x00, 0xF, 0xF, false);
+}
+
+// Minimum over the four lanes of a quad (quad_perm 1,0,3,2 then 2,3,0,1);
+// every lane of the quad gets it.
+__device__ __forceinline__ uint64_t quad_min_u64(uint64_t k) {
+  uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)k, 0xB1, 0xF, 0xF, false);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(k >> 32), 0xB1, 0xF, 0xF, false);
+  uint64_t o = ((uint64_t)hi << 32) | lo;
+  k = o < k ? o : k;
+  lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)k, 0x4E, 0xF, 0xF, false);
+  hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(k >> 32), 0x4E, 0xF, 0xF, false);
+  o = ((uint64_t)hi << 32) | lo;
+  return o < k ? o : k;
+}
+
+// Half-pel resolve with four lanes per block, for frames of at most 256
+// block rows.  Each lane of a block's quad prefetches the record's header,
+// e[0..4] and, as lane q, winner q's 8 prepared half-pel SADs (overflow
+// entries 8q .. 8q+7).  A block with at most four possible winners (and
+// prepared SADs) is decided by its quad: lane q prices winner q, a quad
+// minimum gives the integer winner, and its lane finishes the half-pel step
+// with its SADs (e[1..4] for a single winner).  Blocks with more winners go
+// to the LDS list and whole waves, as in resolve_pair_half.
+struct HalfPart {
+  u32x4 hd;   // sad_min, count, intra_x, pad
+  u32x4 e03;  // e[0..3]
+  uint32_t e4;
+  u32x4 hs;   // winner q's prepared SADs
+};
+
+__device__ __forceinline__ void load_half_part(const BlockRec* __restrict__ recs,
+                                               const uint16_t* __restrict__ ovf, int p, int b,
+                                               int q, HalfPart& r) {
+  if (b < 0) return;
+  const char* rb = reinterpret_cast<const char*>(recs + b);
+  r.hd = ld_global_x4(rb);
+  r.e03 = ld_global_x4(rb + 16);
+  r.e4 = ld_global<uint32_t>(rb + 32);
+  // only inside this block's overflow region (ovf_stride(p) entries)
+  if (8 * q + 8 <= (int)ovf_stride(p)) r.hs = ld_global_x4(ovf + (size_t)b * ovf_stride(p) + 8 * q);
+}
+
+__device__ __forceinline__ void resolve_pair_half4(const KGeom& g,
+                                                   const BlockRec* __restrict__ recs,
+                                                   const uint16_t* __restrict__ ovf,
+                                                   acbm_block_result* __restrict__ out,
+                                                   uint32_t lam, uint32_t* st,
+                                                   const uint8_t* __restrict__ cur,
+                                                   const uint8_t* __restrict__ ref) {
+  const int p = g.p, bx = g.bx, by = g.by;
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int steps = (bx - 1) + 2 * (by - 1) + 1;
+  const int i = (int)threadIdx.x >> 2, q = (int)threadIdx.x & 3;  // block slot, quad lane
+  const uint32_t lim = min(4u, half_cap(p));  // winners a quad decides
+  MultiList& ml = multi_list();
+  if (threadIdx.x < 2) ml.cnt[threadIdx.x] = 0;
+  __syncthreads();
+  HalfPart h{}, hn{};
+  uint32_t sink = 0, touched = 0;
+  int b = step_block(g, 0, i);
+  load_half_part(recs, ovf, p, b, q, h);
+  for (int k = 0; k < steps; ++k) {
+    const int bn = step_block(g, k + 1, i);
+    load_half_part(recs, ovf, p, bn, q, hn);  // in flight while this step is decided
+    sink ^= touched;                          // last step's word, waited for with the prefetch
+    touched = q == 0 ? touch_rec(recs, step_block(g, k + 2, i)) : 0u;
+    if (threadIdx.x == 0) ml.cnt[(k + 1) & 1] = 0;
+    if (b >= 0) {  // the four lanes of a quad share b and its record
+      const int r = b / bx, c = b - r * bx;
+      int px = 0, py = 0;
+      median_pred(st, b, r, c, bx, &px, &py);  // its neighbours are decided
+      const uint32_t count = h.hd.y;
+      if (count <= lim) {
+        const bool has = (uint32_t)q < count;
+        const uint32_t e = q == 0 ? h.e03.x : q == 1 ? h.e03.y : q == 2 ? h.e03.z : h.e03.w;
+        int u = 0, v = 0;
+        uint64_t key = ~0ull;
+        if (has) {
+          window_uv(e & 0xFFFFu, p, &u, &v);
+          key = int_key<true>(e >> 16, u, v, p, px, py, lam);
+        }
+        const uint64_t k0 = quad_min_u64(key);
+        if (has && key == k0) {  // the integer winner's lane (keys are unique)
+          const uint32_t h4[4] = {count == 1 ? h.e03.y : h.hs.x, count == 1 ? h.e03.z : h.hs.y,
+                                  count == 1 ? h.e03.w : h.hs.z, count == 1 ? h.e4 : h.hs.w};
+          uint32_t sads[8];
+#pragma unroll
+          for (int s2 = 0; s2 < 8; ++s2) sads[s2] = (h4[s2 / 2] >> (16 * (s2 & 1))) & 0xFFFFu;
+          half_finish(g, b, 2 * u, 2 * v, key, sads, px, py, lam, h.hd.z, true, out + b, st + b);
+        }
+      } else if (q == 0) {
+        const int at = atomicAdd(&ml.cnt[k & 1], 1);
+        ml.b[at] = (uint32_t)b;
+        ml.n[at] = count;
+      }
+    }
+    __syncthreads();  // quad decisions and the list
+    const int nm = __builtin_amdgcn_readfirstlane(ml.cnt[k & 1]);
+    if (nm) {
+      for (int j = wave; j < nm; j += nwaves) {
+        const int bb = (int)ml.b[j];
+        const uint32_t cnt = ml.n[j];
+        const int r = bb / bx, c = bb - r * bx;
+        int qx = 0, qy = 0;
+        median_pred(st, bb, r, c, bx, &qx, &qy);
+        const uint16_t* row = ovf + (size_t)bb * ovf_stride(p);
+        if (cnt <= half_cap(p)) {
+          half_decide_prepared(g, recs + bb, row, cnt, bb, qx, qy, lam, out + bb, st + bb);
+        } else {
+          const uint64_t key = wave_block_argmin<true>(recs + bb, row, p, qx, qy, lam);
+          half_decide(g, recs + bb, cur, ref, bb, qx, qy, lam, key, out + bb, st + bb);
+        }
+      }
+      __syncthreads();  // this step's decisions before the next step reads them
+    }
+    b = bn;
+    h = hn;
+  }
+  keep(sink ^ touched);
+}
+
 // Integer resolve: the same anti-diagonal order as the half-pel one.  Each
 // thread prefetches the whole record of its block of the next step (header
 // and the kShort listed winners, 8 x 16 bytes), so that a block with at most
@@ -811,23 +935,6 @@ __device__ __forceinline__ void load_int_part(const BlockRec* __restrict__ recs,
   r.b = ld_global_x4(base + 16);
 }
 
-// Lane 0's value to the four lanes of its quad (DPP quad_perm 0,0,0,0).
-__device__ __forceinline__ uint32_t quad_bcast0(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x00, 0xF, 0xF, false);
-}
-
-// Minimum over the four lanes of a quad (quad_perm 1,0,3,2 then 2,3,0,1).
-__device__ __forceinline__ uint64_t quad_min_u64(uint64_t k) {
-  uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)k, 0xB1, 0xF, 0xF, false);
-  uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(k >> 32), 0xB1, 0xF, 0xF, false);
-  uint64_t o = ((uint64_t)hi << 32) | lo;
-  k = o < k ? o : k;
-  lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)k, 0x4E, 0xF, 0xF, false);
-  hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(k >> 32), 0x4E, 0xF, 0xF, false);
-  o = ((uint64_t)hi << 32) | lo;
-  return o < k ? o : k;
-}
-
 __device__ __forceinline__ void resolve_pair_int4(const KGeom& g,
                                                   const BlockRec* __restrict__ recs,
                                                   const uint16_t* __restrict__ ovf,
@@ -843,13 +950,14 @@ __device__ __forceinline__ void resolve_pair_int4(const KGeom& g,
   MultiList& ml = multi_list();
   if (threadIdx.x < 2) ml.cnt[threadIdx.x] = 0;
   __syncthreads();
-  IntPart h{}, hn{};
+  IntPart h0{}, h1{};
   uint32_t sink = 0, touched = 0;
-  int b = step_block(g, 0, i);
-  load_int_part(recs, b, q, h);
-  for (int k = 0; k < steps; ++k) {
-    const int bn = step_block(g, k + 1, i);
-    load_int_part(recs, bn, q, hn);  // in flight while this step is decided
+  load_int_part(recs, step_block(g, 0, i), q, h0);
+  // One step: decides the blocks of step k from h (prefetched one step
+  // earlier) and prefetches step k + 1 into hn.
+  auto step = [&](int k, const IntPart& h, IntPart& hn) {
+    const int b = step_block(g, k, i);
+    load_int_part(recs, step_block(g, k + 1, i), q, hn);  // in flight while this step is decided
     sink ^= touched;                 // last step's word, waited for with the prefetch
     touched = q == 0 ? touch_rec(recs, step_block(g, k + 2, i)) : 0u;
     if (threadIdx.x == 0) ml.cnt[(k + 1) & 1] = 0;
@@ -904,8 +1012,12 @@ __device__ __forceinline__ void resolve_pair_int4(const KGeom& g,
       }
       __syncthreads();  // this step's decisions before the next step reads them
     }
-    b = bn;
-    h = hn;
+  };
+  // Two steps per iteration with the buffers swapped: no register copy, which
+  // would wait for every memory operation of the step, stores included.
+  for (int k = 0; k < steps; k += 2) {
+    step(k, h0, h1);
+    if (k + 1 < steps) step(k + 1, h1, h0);
   }
   keep(sink ^ touched);
 }
@@ -996,7 +1108,10 @@ __device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __r
                                              const uint8_t* __restrict__ cur,
                                              const uint8_t* __restrict__ ref) {
   if constexpr (HP) {
-    resolve_pair_half(g, recs, ovf, out, lam, st, cur, ref);
+    if (4 * g.by <= (int)blockDim.x)
+      resolve_pair_half4(g, recs, ovf, out, lam, st, cur, ref);
+    else
+      resolve_pair_half(g, recs, ovf, out, lam, st, cur, ref);
   } else {
     if (threadIdx.x == 0) shared[1] = 0;
     __syncthreads();
