@@ -890,20 +890,27 @@ static int row_threads() {
 }
 
 // Row blocking R of the critical search.  When a launch has more block rows
-// than the device has CUs, walkers share CUs and the launch is bound by how
-// many rows are in flight: R = 1, whose walkers need the fewest registers
-// (so the most fit on a CU), was fastest everywhere it was measured.  On the
-// 1920x1088 16x16 p = 32 ACBM sequence (59 pairs): R = 1 6.9 ms, 2 7.3,
-// 4 10.9, 5 7.3 ms.  On the 64-sequence batch, its 8x8 group (28
-// sequences): R = 1 11.8 ms, 2 13.0, 3 14.6, 4 18.4, 5 20.2, 6 21.4 ms; its
-// 16x16 group: R = 1 5.0 ms, 3 5.2 ms.  Otherwise each walker has its CU to
-// itself and the critical search's latency matters: the least issue time
-// per lane, rounds * (QSAD cycles of a task + its loads and pricing), among
-// the R whose ring fits in LDS (a single HD pair: R = 5, 2.0 ms against 2.6
-// ms with R = 3).  ACBM_PRED_R overrides.
-static int pick_rows(const KGeom& g, int nt, size_t total_rows) {
+// than the device has CUs, walkers share CUs and the launch is bound by the
+// rows in flight times the per-block latency.  Measured there (16x16 and
+// 8x8 walkers fit four per CU up to R = 3, 8x8 at R = 1 five):
+//  * 1920x1088 16x16 p = 32 ACBM, 59 pairs: R = 3 6.4 ms, 1 6.9, 2 7.3;
+//    with every block critical R = 3 10.6 ms, 1 11.3, 2 12.1;
+//  * the same at half-pel precision: R = 1 7.7 ms, 3 7.8, 2 8.3;
+//  * the 64-sequence batch's 8x8 group (28 sequences): R = 1 11.8 ms, 2 13.0,
+//    3 14.6, 4 18.4, 5 20.2, 6 21.4; its 16x16 group: R = 1 5.0 ms, 3 5.2.
+// So shared CUs take R = 3 for 16-wide blocks at integer precision and R = 1
+// otherwise.  Alone on its CU, a walker's critical search latency matters:
+// the least issue time per lane, rounds * (QSAD cycles of a task + its loads
+// and pricing), among the R whose ring fits in LDS (a single HD pair: R = 5,
+// 2.0 ms against 2.6 ms with R = 3).  ACBM_PRED_R overrides.
+static int pick_rows(const KGeom& g, int nt, size_t total_rows, bool hp) {
   const bool shared_cus = total_rows > (size_t)device_cus();
   const char* force = std::getenv("ACBM_PRED_R");
+  if (!force && shared_cus) {
+    for (int R = (g.bw == 16 && !hp) ? 3 : 1; R >= 1; --R)
+      if (ring_bytes(ring_for(g, R)) <= (size_t)lds_limit()) return R;
+    return 0;
+  }
   const int nc = g.bw / 4;
   int bestR = 0;
   long best = 0;
@@ -911,7 +918,6 @@ static int pick_rows(const KGeom& g, int nt, size_t total_rows) {
     const RingShape w = ring_for(g, R);
     if (ring_bytes(w) > (size_t)lds_limit()) continue;
     if (force && std::atoi(force) != R) continue;
-    if (!force && shared_cus && R > 1) continue;
     const long rounds = (w.s.quads * w.s.groups + nt - 1) / nt;
     const long cost = rounds * ((long)R * g.bh * nc * 16 + 8L * (R + g.bh - 1) + 160L * R);
     if (!bestR || cost < best) {
@@ -929,7 +935,7 @@ int plan_predictive_group(const KGeom* geoms, int n, bool hp, size_t total_rows,
   for (int i = 1; i < n; ++i)
     if (geoms[i].p > geoms[imax].p) imax = i;
   pl->threads = hp ? 256 : row_threads();
-  pl->R = pick_rows(geoms[imax], pl->threads, total_rows);
+  pl->R = pick_rows(geoms[imax], pl->threads, total_rows, hp);
   if (!pl->R) return fail(ACBM_E_UNSUPPORTED, "search window too large for the predictive kernel");
   pl->lds = 0;
   for (int i = 0; i < n; ++i) pl->lds = std::max(pl->lds, ring_bytes(ring_for(geoms[i], pl->R)));
