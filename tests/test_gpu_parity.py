@@ -248,6 +248,26 @@ def test_full_size_8x8_steps_sampled(subpel):
             assert int(one[f]) == int(got[r, c][f]), (r, c, f, one, got[r, c])
 
 
+@pytest.mark.parametrize("subpel", [0, 1])
+def test_tall_frame_one_lane_resolve(subpel):
+    """64x2064 with 8x8 blocks: 258 block rows, more than a quarter of the
+    resolve group, so the FSBM resolve walks its steps with one lane per
+    block (and whole waves for blocks with many winners).  The top half's
+    texture gives most blocks 2-28 possible winners, the smoother bottom
+    half most blocks more than 28, so every path of the step is taken.  The
+    whole frame is compared with the oracle."""
+    top = synth.texture(1032, 64, 2.5, synth.rng(31))
+    bot = synth.texture(1032, 64, 6.0, synth.rng(33))
+    ref = np.vstack([top, bot])
+    cur = np.vstack([synth.add_noise(np.roll(top, (1, -2), (0, 1)), 1.5, synth.rng(32)),
+                     synth.add_noise(np.roll(bot, (1, -2), (0, 1)), 1.0, synth.rng(34))])
+    prm = acbm.Params(lam=4, qp=4, subpel=subpel)
+    say(f"tall 64x2064 8x8 p=4 lambda=4 subpel={subpel}")
+    got = acbm.to_numpy(acbm.fsbm_frame(dev(cur), dev(ref), 8, 8, 4, prm))
+    want = oracle.fsbm_frame(cur, ref, 8, 8, 4, oparams(prm))
+    same(got, want, f"tall frame subpel={subpel}")
+
+
 def test_deterministic_repeat():
     sc = synth.cif_scene(nframes=4, lam=8)
     prm = acbm.default_params(16, 16, 8)
