@@ -49,7 +49,7 @@ namespace acbm {
 constexpr uint32_t kReady = 0x80000000u;
 constexpr int kMaxCands = 14;             // (0,0), left, 3 above, 9 of the previous field
 constexpr int kFetch = 4;                 // new-column dwords each fetching lane holds
-constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr uint32_t kSpinLimit = 1u << 22;  // polls before a dependency wait gives up
 #ifndef ACBM_PRED_WAVES
 #define ACBM_PRED_WAVES 3  // waves per SIMD the register budget must allow
 #endif
@@ -476,7 +476,7 @@ __device__ __forceinline__ void write_result(acbm_block_result* out, uint32_t* w
 template <int N, int M, int R, int NT, bool HP>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ACBM_PRED_WAVES)))
 k_predictive(const PredArgs* __restrict__ jobs, const uint32_t* __restrict__ order,
-             WsHeader* __restrict__ hdr, uint32_t total_rows) {
+             WsHeader* __restrict__ hdr, uint32_t total_rows, uint32_t spin_limit) {
   extern __shared__ uint32_t ring[];
   constexpr int D = M * N / 4;
   constexpr int NC = N / 4;
@@ -572,7 +572,7 @@ k_predictive(const PredArgs* __restrict__ jobs, const uint32_t* __restrict__ ord
         for (;;) {
           if (dw && !(word & kReady)) word = load_word(dw);
           if (__all(!dw || (word & kReady))) break;
-          if (++spins > kSpinLimit || ((spins & 255) == 0 && status_of(hdr))) {
+          if (++spins > spin_limit || ((spins & 255) == 0 && status_of(hdr))) {
             failed = true;
             break;
           }
@@ -839,7 +839,17 @@ struct PredLaunch {
   WsHeader* hdr;
   uint32_t total_rows;
   size_t lds;
+  uint32_t spin_limit;
 };
+
+// Polls of a dependency wait before it gives up: kSpinLimit, or
+// ACBM_PRED_SPIN_LIMIT (read at every launch), with which tests force the
+// time-out path; the kernel then records the failure and every walker leaves.
+static uint32_t spin_limit() {
+  const char* e = std::getenv("ACBM_PRED_SPIN_LIMIT");
+  const long v = e ? std::atol(e) : 0;
+  return v > 0 ? (uint32_t)std::min<long>(v, (long)kSpinLimit) : kSpinLimit;
+}
 
 template <int N, int M, int NT, bool HP = false>
 static int launch_pred_nmt(const PredLaunch& L, int R, hipStream_t st) {
@@ -858,7 +868,7 @@ static int launch_pred_nmt(const PredLaunch& L, int R, hipStream_t st) {
     const int grid = (int)std::min<size_t>((size_t)device_cus() * per_cu, L.total_rows);    \
     ProfScope ps("predictive", st);                                                          \
     hipLaunchKernelGGL((k_predictive<N, M, RR, NT, HP>), dim3(grid), dim3(NT), L.lds, st,    \
-                       L.jobs, L.order, L.hdr, L.total_rows);                                \
+                       L.jobs, L.order, L.hdr, L.total_rows, L.spin_limit);                  \
     break;                                                                                   \
   }
     ACBM_PRED_R_LIST(ACBM_CASE)
@@ -971,7 +981,7 @@ int launch_predictive_group(int bw, int bh, bool hp, const PredGroupPlan& pl,
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "launching the predictive setup");
-  const PredLaunch L{jobs, order, hdr, total_rows, pl.lds};
+  const PredLaunch L{jobs, order, hdr, total_rows, pl.lds, spin_limit()};
   if (bw == 16 && bh == 16) return launch_pred_nm<16, 16>(L, pl.R, pl.threads, hp, st);
   if (bw == 16 && bh == 8) return launch_pred_nm<16, 8>(L, pl.R, pl.threads, hp, st);
   if (bw == 8 && bh == 16) return launch_pred_nm<8, 16>(L, pl.R, pl.threads, hp, st);
