@@ -268,6 +268,21 @@ def test_tall_frame_one_lane_resolve(subpel):
     same(got, want, f"tall frame subpel={subpel}")
 
 
+@pytest.mark.parametrize("subpel", [0, 1])
+@pytest.mark.parametrize("p", [0, 1, 2])
+def test_small_search_ranges(p, subpel):
+    """p = 0..2, where a block's overflow region is smallest (8-16 entries)
+    and the half-pel quad resolve handles at most half_cap(p) < 4 winners; a
+    smooth texture and a large lambda give blocks several possible winners."""
+    ref = synth.texture(48, 64, 4.0, synth.rng(41))
+    cur = synth.add_noise(np.roll(ref, (1, 1), (0, 1)), 1.0, synth.rng(42))
+    prm = acbm.Params(lam=32, qp=32, subpel=subpel)
+    say(f"small ranges 64x48 8x8 p={p} subpel={subpel}")
+    got = acbm.to_numpy(acbm.fsbm_frame(dev(cur), dev(ref), 8, 8, p, prm))
+    want = oracle.fsbm_frame(cur, ref, 8, 8, p, oparams(prm))
+    same(got, want, f"p={p} subpel={subpel}")
+
+
 def test_deterministic_repeat():
     sc = synth.cif_scene(nframes=4, lam=8)
     prm = acbm.default_params(16, 16, 8)
