@@ -373,14 +373,27 @@ __device__ __forceinline__ uint64_t wave_block_argmin(const BlockRec* __restrict
     // multiply-high with ceil(2^32 / W) (ras < 2^16, W < 2^8)
     const uint32_t W = 2u * (uint32_t)p + 1u;
     const uint32_t inv = (uint32_t)(((1ull << 32) + W - 1) / W);
+    // up to kList entries per lane are loaded before any is used, so a long
+    // list costs about one memory latency per 64 * kList entries
     const uint32_t* __restrict__ list = reinterpret_cast<const uint32_t*>(row);
-    for (uint32_t k = (uint32_t)lane; k < n; k += 64) {
-      const uint32_t e = list[k];
-      const uint32_t ras = e & 0xFFFFu;
-      const uint32_t vq = __umulhi(ras, inv);
-      const int v = (int)vq - p, u = (int)(ras - vq * W) - p;
-      const uint64_t key = int_key<HP>(e >> 16, u, v, p, px, py, lam);
-      best = key < best ? key : best;
+    constexpr int kList = 8;
+    for (uint32_t k0 = (uint32_t)lane; k0 < n; k0 += 64 * kList) {
+      uint32_t e[kList];
+#pragma unroll
+      for (int t = 0; t < kList; ++t) {
+        const uint32_t k = k0 + 64u * t;
+        e[t] = k < n ? list[k] : 0u;
+      }
+#pragma unroll
+      for (int t = 0; t < kList; ++t) {
+        if (k0 + 64u * t < n) {
+          const uint32_t ras = e[t] & 0xFFFFu;
+          const uint32_t vq = __umulhi(ras, inv);
+          const int v = (int)vq - p, u = (int)(ras - vq * W) - p;
+          const uint64_t key = int_key<HP>(e[t] >> 16, u, v, p, px, py, lam);
+          best = key < best ? key : best;
+        }
+      }
     }
   } else if (n <= (uint32_t)kShort) {
     const int k = lane - 4;  // e[k] is dword 4 + k of the record
