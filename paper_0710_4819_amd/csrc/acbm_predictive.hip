@@ -889,14 +889,22 @@ static int launch_pred_nm(const PredLaunch& L, int R, int nt, bool hp, hipStream
   return launch_pred_nmt<N, M, 256>(L, R, st);
 }
 
-// Threads per row walker (128, 256 or 512); ACBM_ROW_THREADS overrides.
-static int row_threads() {
-  static int nt = [] {
-    const char* e = std::getenv("ACBM_ROW_THREADS");
-    const int v = e ? std::atoi(e) : 256;
+// Threads per row walker at integer precision (half-pel walkers always have
+// 256).  A group of several sequences has rows to spare, so more, smaller
+// walkers keep more rows in flight: on the 64-sequence batch its 8x8 group
+// (28 sequences) took 9.6 ms with 128 threads against 11.8 with 256, its
+// 16x16 group (36 sequences) 4.9 against 5.3.  One sequence is bound by its
+// dependency chain instead, and its critical searches want the larger
+// walkers (1920x1088 p = 32, 59 pairs: 10.8 ms with 128 threads against 6.9
+// with 256).  So groups of at least four jobs take 128 threads.
+// ACBM_ROW_THREADS (128, 256 or 512) overrides.
+static int row_threads(int njobs) {
+  const char* e = std::getenv("ACBM_ROW_THREADS");
+  if (e) {
+    const int v = std::atoi(e);
     return (v == 128 || v == 512) ? v : 256;
-  }();
-  return nt;
+  }
+  return njobs >= 4 ? 128 : 256;
 }
 
 // Row blocking R of the critical search.  When a launch has more block rows
@@ -944,7 +952,7 @@ int plan_predictive_group(const KGeom* geoms, int n, bool hp, size_t total_rows,
   int imax = 0;  // the largest window decides which row blockings fit in LDS
   for (int i = 1; i < n; ++i)
     if (geoms[i].p > geoms[imax].p) imax = i;
-  pl->threads = hp ? 256 : row_threads();
+  pl->threads = hp ? 256 : row_threads(n);
   pl->R = pick_rows(geoms[imax], pl->threads, total_rows, hp);
   if (!pl->R) return fail(ACBM_E_UNSUPPORTED, "search window too large for the predictive kernel");
   pl->lds = 0;

@@ -43,10 +43,16 @@ def assert_oracle(name, got, frames, bw, bh, p, prm, algo):
 
 def _walker_jobs():
     """Sequences of uneven geometry and length for every block size, integer
-    and half-pel, PBM and ACBM (16 jobs in 8 groups)."""
+    and half-pel, PBM and ACBM (19 jobs in 8 groups; the integer 16x16 group
+    has five jobs, enough for the smaller walkers of many-job groups)."""
     sc = synth.cif_scene(nframes=6, lam=8)
     hd = synth.hd_scene(nframes=3, lam=8)
-    jobs = []
+    jobs = [([f[32:208, 48:304] for f in sc.frames[:5]], 16, 16, 12, acbm.ALGO_ACBM,
+             params(16, 16, 8)),
+            ([f[:288, :352] for f in sc.frames[:3]], 16, 16, 16, acbm.ALGO_ACBM,
+             params(16, 16, 4, qp=20)),
+            ([f[:128, :192] for f in hd.frames[:3]], 16, 16, 20, acbm.ALGO_PBM,
+             params(16, 16, 8))]
     for bw, bh in ((16, 16), (16, 8), (8, 16), (8, 8)):
         for subpel in (0, 1):
             jobs.append(([f[:144, :176] for f in sc.frames[:6]], bw, bh, 7, acbm.ALGO_ACBM,
@@ -80,7 +86,7 @@ def test_walker_groups_match_the_oracle():
 
 def test_walker_group_graph_replays():
     dev = torch.device("cuda", 0)
-    jobs = _walker_jobs()[:6]
+    jobs = _walker_jobs()[:9]
     b = _batch(dev, jobs)
     eager = [acbm.to_numpy(o.clone()) for o in b.run()]
     ws = torch.empty(max(256, b.workspace_size()), dtype=torch.uint8, device=dev)
