@@ -210,6 +210,14 @@ int acbm_batch_workspace_size(const acbm_job* jobs, size_t njobs, size_t* bytes)
  * launch whose walkers take the block rows of all its jobs in level order
  * (row r of pair t has level r + 2t), so the dependency chains of the jobs
  * run side by side.  A PBM/ACBM job of more than 4095 pairs runs alone.
+ * When `stream` belongs to the current device, the walker launches go to up
+ * to four side streams of that device (created by the library on first use
+ * and kept until the process ends), forked off `stream` after the tables are
+ * written and joined back into it before the call returns: the call stays
+ * ordered on `stream`, and a capture of `stream` records them as parallel
+ * branches.  ACBM_BATCH_STREAMS (0 to 4) caps the side streams; 0 keeps
+ * every launch on `stream`.  Concurrent calls from several host threads are
+ * serialised while they enqueue.
  * ws must hold acbm_batch_workspace_size bytes (per-job scratch plus the
  * tables) and must not be shared by overlapping calls. */
 int acbm_batch(const acbm_job* jobs, size_t njobs, void* ws, size_t ws_bytes, void* stream);

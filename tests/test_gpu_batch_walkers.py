@@ -130,3 +130,52 @@ def test_walker_group_split_at_its_job_limit():
     assert b.status() == 0
     for i, (frames, bw, bh, p, algo, prm) in enumerate(jobs):
         assert_oracle(f"job {i}", got[i], frames, bw, bh, p, prm, algo)
+
+
+def test_side_streams_match_one_stream(monkeypatch):
+    """Walker launches run on side streams forked off the caller's stream,
+    beside the FSBM searches.  A batch that mixes FSBM jobs with several walker
+    groups gives the same results with every launch on one stream
+    (ACBM_BATCH_STREAMS=0), eagerly and on graph replays, and its FSBM jobs
+    match the oracle."""
+    dev = torch.device("cuda", 0)
+    sc = synth.cif_scene(nframes=4, lam=8)
+    jobs = _walker_jobs()[:7]
+    fsbm = [([f[:144, :176] for f in sc.frames[:4]], 16, 16, 7, acbm.ALGO_FSBM,
+             params(16, 16, 8)),
+            ([f[:96, :128] for f in sc.frames[:3]], 8, 8, 5, acbm.ALGO_FSBM,
+             params(8, 8, 4, subpel=1))]
+    jobs = fsbm[:1] + jobs + fsbm[1:]
+    b = _batch(dev, jobs)
+    ws = torch.empty(max(256, b.workspace_size()), dtype=torch.uint8, device=dev)
+    monkeypatch.setenv("ACBM_BATCH_STREAMS", "0")
+    say(f"mixed batch of {len(jobs)} jobs on one stream")
+    one = [acbm.to_numpy(o.clone()) for o in b.run(ws)]
+    torch.cuda.synchronize()
+    assert b.status(ws) == 0
+    monkeypatch.delenv("ACBM_BATCH_STREAMS")
+    for o in b.outs:
+        o.fill_(0x5A)
+    say("the same batch on side streams, eager")
+    side = [acbm.to_numpy(o.clone()) for o in b.run(ws)]
+    torch.cuda.synchronize()
+    assert b.status(ws) == 0
+    for i in range(len(jobs)):
+        assert np.array_equal(side[i], one[i]), f"eager, job {i}"
+    gr = acbm.BatchGraph(b, ws)
+    try:
+        for rep in range(3):
+            for o in b.outs:
+                o.fill_(0xA5)
+            say(f"side-stream graph replay {rep}")
+            outs = gr.launch()
+            torch.cuda.synchronize()
+            for i, o in enumerate(outs):
+                assert np.array_equal(acbm.to_numpy(o), one[i]), f"replay {rep}, job {i}"
+            x = torch.randn(1 << 18, device=dev)
+            _ = (x * 2).sum().item()
+    finally:
+        gr.close()
+    for i in (0, len(jobs) - 1):
+        frames, bw, bh, p, algo, prm = jobs[i]
+        assert_oracle(f"job {i}", one[i], frames, bw, bh, p, prm, algo)
