@@ -125,7 +125,8 @@ def batched_leg(torch, acbm, synth, dev, reps=5):
     """64 sequences x 8 frames of mixed resolution, p and block size: the
     graph-recorded FSBM batch against the eager batch call and against one
     acbm_fsbm_frame call per frame pair, and the same sequences as one
-    graph-recorded ACBM batch, all on one stream, inputs resident."""
+    graph-recorded ACBM batch, all launched on one stream (the library forks
+    its walker launches onto side streams and joins them back), inputs resident."""
     seqs = [synth.batch_sequence(s) for s in range(64)]
     # tune each (block size, p) on the largest frame that uses it
     largest = {}
