@@ -129,7 +129,11 @@ const char* acbm_version(void);
 const char* acbm_strerror(int status);
 /* Detail of the last failing call on this thread ("" if none). */
 const char* acbm_last_error(void);
-/* Checks that the current HIP device is gfx950 (ACBM_E_UNSUPPORTED if not). */
+/* Checks that the current HIP device is gfx950 (ACBM_E_UNSUPPORTED if not)
+ * and creates the side streams acbm_batch uses on it.  Optional: without it
+ * they are created at the first batch that needs them, which a stream capture
+ * in hipStreamCaptureModeGlobal refuses, so call it once per device before
+ * capturing acbm_batch in that mode. */
 int acbm_init(void);
 
 /* Bytes of device workspace an operation needs for `npairs` frame pairs of

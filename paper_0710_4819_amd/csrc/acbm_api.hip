@@ -238,7 +238,8 @@ const char* acbm_last_error(void) { return t_last_error.c_str(); }
 
 int acbm_init(void) {
   t_last_error.clear();
-  return check_device();
+  const int rc = check_device();
+  return rc ? rc : batch_side_streams_init();
 }
 
 int acbm_workspace_size(int op, const acbm_geom* g, uint32_t npairs, size_t* bytes) {

@@ -356,6 +356,21 @@ int side_pool(int dev, SidePool** out) {
 int enqueue_fsbm(const acbm_job* jobs, const Plan& pl, char* base, const BatchJob* all,
                  hipStream_t st);
 
+}  // namespace
+
+// Creates the current device's side streams now rather than at the first
+// batch that forks (where a global-mode stream capture would refuse it).
+int acbm::batch_side_streams_init() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  SidePool* sp = nullptr;
+  return side_pool(dev, &sp);
+}
+
+namespace {
+
 // Enqueues every job of a validated batch, ordered on `st`: the job tables
 // first; then one row-walker launch per PBM/ACBM group and one for each
 // PBM/ACBM job that runs alone, on side streams forked off `st`; then one

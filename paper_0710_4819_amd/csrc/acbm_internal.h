@@ -154,6 +154,8 @@ bool fsbm_mv_in_lds(const KGeom& g);
 // of a set of FSBM jobs (one workgroup per pair).
 int launch_search_batch(int N, int M, const SearchPlan& pl, size_t lds, const BatchJob* jobs,
                         int njobs, uint32_t items, hipStream_t s);
+// Creates the current device's side streams for batch walker launches.
+int batch_side_streams_init();
 int launch_resolve_batch(const BatchJob* jobs, int njobs, uint32_t pairs, size_t lds,
                          hipStream_t s);
 size_t predictive_ws_bytes(const KGeom& g, uint32_t npairs);

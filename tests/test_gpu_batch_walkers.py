@@ -179,3 +179,38 @@ def test_side_streams_match_one_stream(monkeypatch):
     for i in (0, len(jobs) - 1):
         frames, bw, bh, p, algo, prm = jobs[i]
         assert_oracle(f"job {i}", one[i], frames, bw, bh, p, prm, algo)
+
+
+def test_global_mode_capture_after_init():
+    """After acbm_init (which creates the side streams), an acbm_batch call
+    whose walker launches fork onto side streams can be captured into a torch
+    CUDA graph in global capture mode; every replay equals the eager run."""
+    dev = torch.device("cuda", 0)
+    assert acbm.lib().acbm_init() == 0
+    sc = synth.cif_scene(nframes=4, lam=8)
+    jobs = [([f[:144, :176] for f in sc.frames[:4]], 16, 16, 7, acbm.ALGO_FSBM,
+             params(16, 16, 8))] + _walker_jobs()[:5]
+    b = _batch(dev, jobs)
+    ws = torch.empty(max(256, b.workspace_size()), dtype=torch.uint8, device=dev)
+    eager = [acbm.to_numpy(o.clone()) for o in b.run(ws)]
+    torch.cuda.synchronize()
+    assert b.status(ws) == 0
+    s = torch.cuda.Stream(device=dev)
+    g = torch.cuda.CUDAGraph()
+    say("capturing acbm_batch in global mode")
+    with torch.cuda.graph(g, stream=s, capture_error_mode="global"):
+        b.run(ws, s)
+    for rep in range(3):
+        for o in b.outs:
+            o.fill_(0x3C)
+        say(f"captured batch replay {rep}")
+        g.replay()
+        torch.cuda.synchronize()
+        for i, o in enumerate(b.outs):
+            assert np.array_equal(acbm.to_numpy(o), eager[i]), f"replay {rep}, job {i}"
+        x = torch.randn(1 << 18, device=dev)
+        _ = (x * 2).sum().item()
+    assert b.status(ws) == 0
+    for i in (0, 1):
+        frames, bw, bh, p, algo, prm = jobs[i]
+        assert_oracle(f"job {i}", eager[i], frames, bw, bh, p, prm, algo)
