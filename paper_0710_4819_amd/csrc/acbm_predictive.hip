@@ -558,10 +558,14 @@ k_predictive(const PredArgs* __restrict__ jobs, const uint32_t* __restrict__ ord
           const int rr = r + (lane - 5) / 3 - 1, cc = c + (lane - 5) % 3 - 1;
           if (rr >= 0 && rr < by && cc >= 0 && cc < bx) {
             if (a.prev0) {
-              // acbm_mv: x in the low, y in the high 16 bits
+              // acbm_mv: x in the low, y in the high 16 bits.  A component
+              // beyond +-127 would wrap in the packed byte; no such vector
+              // is a valid candidate (p <= 127), so it is dropped here as
+              // the validity test would drop it.
               const uint32_t m =
                   ld_global<uint32_t>(a.prev0 + (size_t)(rr * bx + cc) * a.prev0_stride);
-              val = pack_mv((int16_t)(m & 0xFFFFu), (int16_t)(m >> 16));
+              const int mx = (int16_t)(m & 0xFFFFu), my = (int16_t)(m >> 16);
+              if (mx >= -127 && mx <= 127 && my >= -127 && my <= 127) val = pack_mv(mx, my);
             } else {
               val = pack_mv(0, 0);
             }

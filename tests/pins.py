@@ -693,6 +693,55 @@ ALL_PINS += [pin_half_sample_values, pin_half_sample_brute, pin_half_valid_and_s
              pin_brute_half, pin_half_table1_count, pin_half_planted]
 
 
+def _hostile_prev(cur, bw, bh, p, s, seed):
+    """A previous field in which most blocks carry a vector that is not a
+    valid candidate: beyond +-s*p, beyond a signed byte, at the int16 limits,
+    and values that equal a small valid vector modulo 256."""
+    by, bx = cur.shape[0] // bh, cur.shape[1] // bw
+    special = [(256, 1), (200, 0), (-200, 3), (128, 0), (-129, -1), (-32768, 0), (32767, 1),
+               (0, -32768), (s * p + 1, 0), (0, -(s * p + 1)), (2 * s * p + 1, 1), (-253, 2),
+               (259, -1), (1, 258)]
+    g = synth.rng(seed)
+    prev = g.integers(-s * p, s * p + 1, size=(by, bx, 2)).astype(np.int16)
+    for r in range(by):
+        for c in range(bx):
+            if g.random() < 0.7:
+                prev[r, c] = special[int(g.integers(0, len(special)))]
+    return prev
+
+
+def pin_brute_hostile_prev():
+    """Section 2.2's predictor set takes the previous field's vectors as
+    candidates; one that is not a valid candidate is dropped (not clamped,
+    not wrapped).  PBM and ACBM with such fields, at integer and half-pel
+    precision, against the brute force."""
+    for i, (cur, ref, bw, bh, p) in enumerate(_tiny_cases()):
+        if i % 2:
+            continue
+        subpel = (i // 2) % 2
+        s = 2 if subpel else 1
+        lam = [0, 1, 4, 32][(i // 2) % 4]
+        prev = _hostile_prev(cur, bw, bh, p, s, 1200 + i)
+        pv = {(r, c): (int(prev[r, c, 0]), int(prev[r, c, 1]))
+              for r in range(prev.shape[0]) for c in range(prev.shape[1])}
+        cl, rl = brute.as_lists(cur), brute.as_lists(ref)
+        got = oracle.pbm_frame(cur, ref, bw, bh, p, oracle.Params(lam=lam, subpel=subpel),
+                               prev_field=prev)
+        _same(got, brute.predictive(cl, rl, bw, bh, p, lam, prev=pv, half=bool(subpel)),
+              f"hostile pbm case {i}")
+        nm = bw * bh
+        prm = oracle.Params(lam=lam, qp=lam, alpha=[0, 3, 40, 1000][i % 4] * nm // 16,
+                            beta=[0, 1, 2, 8][(i // 4) % 4], gamma_num=1,
+                            gamma_den=[1, 4, 2, 4][(i // 2) % 4], subpel=subpel)
+        got = oracle.acbm_frame(cur, ref, bw, bh, p, prm, prev_field=prev)
+        want = brute.predictive(cl, rl, bw, bh, p, lam, prev=pv, half=bool(subpel),
+                                acbm=(prm.alpha, prm.beta, prm.qp, prm.gamma_num, prm.gamma_den))
+        _same(got, want, f"hostile acbm case {i}")
+
+
+ALL_PINS.append(pin_brute_hostile_prev)
+
+
 if __name__ == "__main__":
     import sys
     bad = run_all(sys.argv[1] if len(sys.argv) > 1 else None)

@@ -78,6 +78,8 @@ MUTATIONS = [
      "if (!oracle_is_valid(g, r, c, pu[k], pv[k])) continue;"),
     ("half_rate_integer_units", "e.rate = (uint32_t)(oracle_se_bits((int64_t)u - px) + oracle_se_bits((int64_t)v - py));",
      "e.rate = (uint32_t)(oracle_se_bits(((int64_t)u - px) / units(prm)) + oracle_se_bits(((int64_t)v - py) / units(prm)));"),
+    ("prev_wraps_to_byte", "pu[np] = prev_field ? prev_field[2 * (rr * bx + cc) + 0] : 0;\n            pv[np] = prev_field ? prev_field[2 * (rr * bx + cc) + 1] : 0;",
+     "pu[np] = prev_field ? (int8_t)prev_field[2 * (rr * bx + cc) + 0] : 0;\n            pv[np] = prev_field ? (int8_t)prev_field[2 * (rr * bx + cc) + 1] : 0;"),
     ("seq_field_transposed", "prev[2 * b + 0] = (int16_t)o[b].mv_x;\n            prev[2 * b + 1] = (int16_t)o[b].mv_y;",
      "prev[2 * b + 0] = (int16_t)o[b].mv_y;\n            prev[2 * b + 1] = (int16_t)o[b].mv_x;"),
 ]
