@@ -73,15 +73,52 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the served-requests leg")
     ap.add_argument("--serve-seconds", type=float, default=1.5,
                     help="duration of each arrival rate of the served leg")
+    ap.add_argument("--walker-phases", action="store_true",
+                    help="report the row walkers' per-phase times (needs the profiling build: "
+                         "ACBM_LIB=paper_0710_4819_amd/libacbm_phases.so, built by "
+                         "`python -m paper_0710_4819_amd.build --phases`)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB, so that "
                          "hardware byte counters can be scaled against a known transfer")
     return ap.parse_args()
 
 
+def log(msg):
+    """Progress of the run, on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def host_info():
+    """The host the oracle is timed on: CPU model, cores, compiler and flags."""
+    import subprocess
+    from oracle import build as oracle_build
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    cc = os.environ.get("CC", "gcc")
+    try:
+        ver = subprocess.run([cc, "--version"], capture_output=True, text=True,
+                             timeout=30).stdout.splitlines()[0]
+    except (OSError, IndexError, subprocess.SubprocessError):
+        ver = cc
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable,
+            "compiler": ver, "flags": " ".join(oracle_build.CFLAGS)}
+
+
 def cpu_baseline(wl, prm_oracle):
     """The plain C oracle (one thread) on a bounded sample: FSBM and ACBM of
-    the first frame pair of the same sequence."""
+    the first frame pair of the same sequence.  Returns the timing record and
+    the two oracle result arrays."""
     import oracle
     cur, ref = wl.frames[1], wl.frames[0]
     t0 = time.perf_counter()
@@ -89,17 +126,18 @@ def cpu_baseline(wl, prm_oracle):
     a = oracle.acbm_frame(cur, ref, 16, 16, 32, prm_oracle)
     dt = time.perf_counter() - t0
     evals = (int(f["cands"].astype(np.int64).sum()) + int(a["cands"].astype(np.int64).sum())) * 256
-    return {"value": evals / dt, "unit": "candidate-pixel SAD evals/s", "cores": 1, "kind": "oracle",
-            "sample": "FSBM + ACBM of pair 1 of the 1920x1088 p=32 sequence, single thread, "
-                      f"{dt:.1f} s, {evals / 1e9:.2f} G evals",
-            "seconds": round(dt, 2)}
+    return ({"value": evals / dt, "unit": "candidate-pixel SAD evals/s", "cores": 1,
+             "kind": "oracle",
+             "sample": "FSBM + ACBM of pair 1 of the 1920x1088 p=32 sequence, single thread, "
+                       f"{dt:.1f} s, {evals / 1e9:.2f} G evals",
+             "seconds": round(dt, 2)}, f, a)
 
 
 def cpu_baseline_parallel(wl, prm_oracle, threads=16):
     """The same oracle, unchanged, on several frame pairs at once: one pair
     per thread (ctypes releases the interpreter lock around each C call), as
-    many threads as the host's share of cores allows, at most 16."""
-    import os
+    many threads as the host's share of cores allows, at most 16.  Returns the
+    timing record and the oracle's FSBM result of every pair it ran."""
     from concurrent.futures import ThreadPoolExecutor
     import oracle
     n = max(1, min(threads, os.cpu_count() or 1, len(wl.frames) - 1))
@@ -108,17 +146,58 @@ def cpu_baseline_parallel(wl, prm_oracle, threads=16):
         cur, ref = wl.frames[t], wl.frames[t - 1]
         f = oracle.fsbm_frame(cur, ref, 16, 16, 32, prm_oracle)
         a = oracle.acbm_frame(cur, ref, 16, 16, 32, prm_oracle)
-        return (int(f["cands"].astype(np.int64).sum()) + int(a["cands"].astype(np.int64).sum())) * 256
+        return f, (int(f["cands"].astype(np.int64).sum()) + int(a["cands"].astype(np.int64).sum())) * 256
 
     oracle.se_bits(0)  # load the library before the threads start
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=n) as ex:
-        evals = sum(ex.map(one, range(1, n + 1)))
+        outs = list(ex.map(one, range(1, n + 1)))
     dt = time.perf_counter() - t0
-    return {"value": evals / dt, "unit": "candidate-pixel SAD evals/s", "cores": n, "kind": "oracle",
-            "sample": f"FSBM + ACBM of pairs 1..{n} of the 1920x1088 p=32 sequence, one pair per "
-                      f"thread, {dt:.1f} s, {evals / 1e9:.2f} G evals",
-            "seconds": round(dt, 2)}
+    evals = sum(e for _, e in outs)
+    return ({"value": evals / dt, "unit": "candidate-pixel SAD evals/s", "cores": n,
+             "kind": "oracle",
+             "sample": f"FSBM + ACBM of pairs 1..{n} of the 1920x1088 p=32 sequence, one pair per "
+                       f"thread, {dt:.1f} s, {evals / 1e9:.2f} G evals",
+             "seconds": round(dt, 2)}, [f for f, _ in outs])
+
+
+RESULT_FIELDS = ("mv_x", "mv_y", "sad", "j", "rate_bits", "cands", "mode", "intra_x")
+
+
+def count_mismatches(got, want):
+    """Blocks of one frame pair where any result field differs."""
+    bad = np.zeros(want.shape, dtype=bool)
+    for f in RESULT_FIELDS:
+        bad |= got[f].astype(np.int64) != want[f].astype(np.int64)
+    return int(bad.sum())
+
+
+def probe_peak():
+    """Runs the SAD-instruction probe (probe/probe_sad, built by
+    probe/build.py) when it is there, and returns its issue costs, byte-diff
+    rates and measured shader clock: the evidence behind the peak."""
+    import re
+    import subprocess
+    exe = os.path.join(os.path.dirname(os.path.abspath(__file__)), "probe", "probe_sad")
+    if not os.path.exists(exe):
+        return None
+    try:
+        txt = subprocess.run([exe], capture_output=True, text=True, timeout=120).stdout
+    except (OSError, subprocess.SubprocessError):
+        return None
+    out = {"source": "probe/probe_sad"}
+    m = re.search(r"issue cost relative to a full-rate op: sad_u8 ([0-9.]+), qsad ([0-9.]+)", txt)
+    if m:
+        out["issue_cost_sad_u8"], out["issue_cost_qsad"] = float(m.group(1)), float(m.group(2))
+    for op in ("v_sad_u8", "v_qsad_pk_u16_u8"):
+        m = re.search(op + r"\s+[0-9.]+ ms\s+[0-9.]+ T lane-ops/s\s+([0-9.]+) T byte-diffs/s", txt)
+        if m:
+            out[op + "_T_byte_diffs_per_s"] = float(m.group(1))
+    m = re.search(r"min ([0-9.]+), median ([0-9.]+), max ([0-9.]+) MHz", txt)
+    if m:
+        out["clock_mhz"] = {"min": float(m.group(1)), "median": float(m.group(2)),
+                            "max": float(m.group(3))}
+    return out
 
 
 def batched_leg(torch, acbm, synth, dev, reps=5):
@@ -281,56 +360,137 @@ def latency_leg(torch, acbm, frames, prm, stream, reps=5):
     return out
 
 
-def served_leg(acbm, synth, rates, seconds, nstreams=32, nfr=3):
-    """Poisson arrivals of frame-pair FSBM requests over 32 streams whose
+def served_leg(torch, acbm, synth, rates, seconds, algo_names=("fsbm", "acbm"), nstreams=32,
+               nfr=3, sat_requests=3000):
+    """Poisson arrivals of frame-pair requests over 32 streams whose
     resolution (640x480 .. 3840x2160) and p (16, 32, 64) are drawn per stream;
-    each stream cycles over nfr generated frames.  Latency is submit ->
-    result on the host (includes the frame upload and the result download)."""
+    each stream cycles over nfr generated frames.  The server gathers the
+    requests into passes (continuous batching) on 4 lanes.  Latency is submit
+    -> result on the host (it includes the frame upload and the result
+    download).  Per algorithm: each offered rate, then saturation (every
+    request submitted at once).  The same request mix run as plain
+    acbm_fsbm_frame calls, one after another on one stream with the frames
+    already on the device, gives the per-frame FSBM rate the served rates are
+    compared with."""
     specs = synth.serve_streams(nstreams)
     frames = [synth.stream_frames(sp, nfr) for sp in specs]
+    prm = acbm.default_params(16, 16, 8)
     out = {"workload": f"{nstreams} streams, 640x480..3840x2160, p 16/32/64, 16x16 blocks, "
-                       "lambda 8, FSBM, Poisson arrivals", "rates": {}}
-    for rate in rates:
-        n = max(1, int(rate * seconds))
-        times, sids = synth.serve_arrivals(rate, n, nstreams)
-        srv = acbm.Server(pool_bytes=24 << 30, max_streams=nstreams, max_inflight=16,
-                          queue_depth=8192)
+                       "lambda 8, Poisson arrivals", "lanes": 4, "max_inflight": 64}
+    algos = {"fsbm": acbm.ALGO_FSBM, "acbm": acbm.ALGO_ACBM, "pbm": acbm.ALGO_PBM}
+
+    def one_rate(algo, rate, n, nthreads=4):
+        """Submitting threads: thread i owns the streams s % nthreads == i and
+        submits their arrivals in time order (the copy into the server's
+        staging runs outside the interpreter lock, so the threads copy in
+        parallel)."""
+        import threading
+        times, sids = synth.serve_arrivals(rate if rate else 1e9, n, nstreams)
+        srv = acbm.Server(pool_bytes=24 << 30, max_streams=nstreams, max_inflight=64,
+                          queue_depth=16384, lanes=4, pinned_bytes=2 << 30)
         try:
-            prm = acbm.default_params(16, 16, 8)
-            first = [srv.submit(s, frames[s][0], 16, 16, specs[s]["p"], prm, acbm.ALGO_FSBM)
+            first = [srv.submit(s, frames[s][0], 16, 16, specs[s]["p"], prm, algo)
                      for s in range(nstreams)]
             for t in first:
                 srv.wait(t)
-            nxt = [1] * nstreams
-            tickets, busy = [], 0
-            t0 = time.perf_counter()
-            for k in range(n):
-                target = t0 + float(times[k])
-                while True:
-                    now = time.perf_counter()
-                    if now >= target:
-                        break
-                    time.sleep(min(0.0005, target - now))
-                s = int(sids[k])
+            base = srv.stats()
+            tickets = [[] for _ in range(nthreads)]
+            busy = [0] * nthreads
+            errors = []
+
+            def submitter(i, t0):
+                nxt = {}
                 try:
-                    tickets.append(srv.submit(s, frames[s][nxt[s] % nfr], 16, 16, specs[s]["p"],
-                                              prm, acbm.ALGO_FSBM))
-                    nxt[s] += 1
-                except acbm.AcbmError as e:
-                    if e.status != acbm.E_BUSY:
-                        raise
-                    busy += 1
-            for t in tickets:
-                srv.wait(t)
+                    for k in range(n):
+                        s = int(sids[k])
+                        if s % nthreads != i:
+                            continue
+                        if rate:
+                            target = t0 + float(times[k])
+                            while True:
+                                now = time.perf_counter()
+                                if now >= target:
+                                    break
+                                time.sleep(min(0.0005, target - now))
+                        j = nxt.get(s, 1)
+                        try:
+                            tickets[i].append(srv.submit(s, frames[s][j % nfr], 16, 16,
+                                                         specs[s]["p"], prm, algo))
+                            nxt[s] = j + 1
+                        except acbm.AcbmError as e:
+                            if e.status != acbm.E_BUSY:
+                                raise
+                            busy[i] += 1
+                except Exception as e:  # reported by the main thread
+                    errors.append(e)
+
+            t0 = time.perf_counter()
+            th = [threading.Thread(target=submitter, args=(i, t0)) for i in range(nthreads)]
+            for x in th:
+                x.start()
+            for x in th:
+                x.join()
+            if errors:
+                raise errors[0]
+            evals = 0
+            for tl in tickets:
+                for t in tl:
+                    r = srv.wait(t)
+                    evals += int(r["cands"].astype(np.int64).sum()) * 256
             t1 = time.perf_counter()
             stt = srv.stats()
+            tickets = [t for tl in tickets for t in tl]
+            busy = sum(busy)
         finally:
             srv.close()
-        out["rates"][str(rate)] = {"offered_rps": rate, "requests": n, "completed": int(stt["completed"]),
-                                   "rejected_busy": busy, "achieved_rps": len(tickets) / (t1 - t0),
-                                   "p50_ms": stt["p50_us"] / 1e3, "p99_ms": stt["p99_us"] / 1e3,
-                                   "mean_ms": stt["mean_us"] / 1e3,
-                                   "gpu_busy_frac": stt["gpu_busy_frac"]}
+        done = int(stt["completed"] - base["completed"])
+        return {"offered_rps": rate if rate else "saturation", "requests": n, "completed": done,
+                "rejected_busy": busy, "achieved_rps": len(tickets) / (t1 - t0),
+                "evals_per_s": evals / (t1 - t0),
+                "p50_ms": stt["p50_us"] / 1e3, "p99_ms": stt["p99_us"] / 1e3,
+                "mean_ms": stt["mean_us"] / 1e3,
+                "device_busy_frac": stt["device_busy_frac"],
+                "passes": int(stt["passes"] - base["passes"]),
+                "mean_batch": (done / max(1, stt["passes"] - base["passes"]))}
+
+    for name in algo_names:
+        algo = algos[name]
+        res = {"rates": {}}
+        for rate in rates:
+            res["rates"][str(rate)] = one_rate(algo, rate, max(1, int(rate * seconds)))
+            log(f"served {name} at {rate} req/s: {res['rates'][str(rate)]['achieved_rps']:.0f} req/s")
+        res["saturation"] = one_rate(algo, 0, sat_requests)
+        log(f"served {name} saturated: {res['saturation']['achieved_rps']:.0f} req/s")
+        out[name] = res
+    # the same mix as plain per-frame FSBM calls, frames resident, one stream
+    dev = torch.device("cuda", 0)
+    dfr = [[torch.from_numpy(f).to(dev) for f in fr] for fr in frames]
+    wss = [acbm.workspace(acbm.OP_FSBM, acbm.geom(dfr[s][0], 16, 16, specs[s]["p"]), dev)
+           for s in range(nstreams)]
+    _, sids = synth.serve_arrivals(1000.0, 400, nstreams)
+    st = torch.cuda.Stream(device=dev)
+    outs = [torch.empty((f[0].shape[0] // 16, f[0].shape[1] // 16, 32), dtype=torch.uint8,
+                        device=dev) for f in dfr]
+
+    def per_frame(k0, k1):
+        for k in range(k0, k1):
+            s = int(sids[k])
+            acbm.fsbm_frame(dfr[s][1 + k % (nfr - 1)], dfr[s][k % (nfr - 1)], 16, 16,
+                            specs[s]["p"], prm, ws=wss[s], stream=st)
+
+    with torch.cuda.stream(st):
+        per_frame(0, 32)  # warm-up
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        per_frame(0, len(sids))
+        e1.record(st)
+    torch.cuda.synchronize()
+    pf_rps = len(sids) / (e0.elapsed_time(e1) / 1e3)
+    out["per_frame_fsbm_rps"] = pf_rps
+    out["per_frame_fsbm_note"] = ("400 requests of the same mix through acbm_fsbm_frame, one "
+                                  "after another on one stream, frames already on the device")
+    for name in algo_names:
+        out[name]["saturation_vs_per_frame_fsbm"] = out[name]["saturation"]["achieved_rps"] / pf_rps
     return out
 
 
@@ -394,6 +554,9 @@ def main():
     if do_a:
         assert ac.status(ws_a, stream) == 0, "ACBM dependency wait timed out"
 
+    if args.walker_phases and acbm.phase_profile_read(reset=True) is None:
+        print("--walker-phases needs the phase-profiling build (ACBM_LIB)", file=sys.stderr)
+        sys.exit(2)
     acbm.profile_enable(True)
     acbm.profile_reset()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
@@ -454,24 +617,57 @@ def main():
                                             if traffic else None),
                            "kernel": "k_search (FSBM window search, QSAD)",
                            "launch_ms": search_ms / search_n}
+    log(f"timed steps done: {ms_step:.2f} ms per step")
+    if args.walker_phases:
+        ph = acbm.phase_profile_read(reset=True)
+        nblk, ncrit = max(1, ph["blocks"]), max(1, ph["critical_blocks"])
+        us = lambda k, n: ph[k] / 100.0 / n  # s_memrealtime ticks at 100 MHz -> us
+        out["walker_phases"] = {
+            "blocks": ph["blocks"], "critical_blocks": ph["critical_blocks"],
+            "us_per_block": {k: us(k, nblk) for k in ("dependency_wait", "phase_a", "phase_b",
+                                                      "phase_c")},
+            "critical_search_us_per_critical_block": us("critical_search", ncrit),
+            "row_setup_us_per_row": us("row_setup", max(1, ph["blocks"] // 120)),
+            "note": "thread 0 of each walker, s_memrealtime stamps; profiling build"}
     if do_f and do_a and len(frames) >= 32:
         out["latency_one_pair"] = latency_leg(torch, acbm, frames, prm, stream)
     if args.only in (None, "halfpel"):
         out["halfpel"] = halfpel_leg(torch, acbm, frames, prm, stream, args.steps)
+        log("half-pel leg done")
     if args.only in (None, "batch") and not args.no_batch:
         out["batched"] = batched_leg(torch, acbm, synth, dev)
+        log("batched leg done")
     if args.only in (None, "serve") and not args.no_serve:
-        out["served"] = served_leg(acbm, synth, [200, 500, 1000, 2000], args.serve_seconds)
+        out["served"] = served_leg(torch, acbm, synth, [200, 500, 1000, 2000], args.serve_seconds)
+    if do_f and "roofline" in out:
+        ev = probe_peak()
+        if ev:
+            out["roofline"]["peak_evidence"] = ev
+    mismatches = 0
     if not args.no_cpu:
+        log("oracle baseline and parity check")
         import oracle
-        out["cpu_baseline"] = cpu_baseline(wl, oracle.Params(lam=prm.lam, qp=prm.qp, alpha=prm.alpha,
-                                                             beta=prm.beta, gamma_num=prm.gamma_num,
-                                                             gamma_den=prm.gamma_den))
-        out["cpu_baseline"]["host"] = platform.processor() or platform.machine()
-        out["cpu_baseline_parallel"] = cpu_baseline_parallel(
-            wl, oracle.Params(lam=prm.lam, qp=prm.qp, alpha=prm.alpha, beta=prm.beta,
-                              gamma_num=prm.gamma_num, gamma_den=prm.gamma_den))
+        oprm = oracle.Params(lam=prm.lam, qp=prm.qp, alpha=prm.alpha, beta=prm.beta,
+                             gamma_num=prm.gamma_num, gamma_den=prm.gamma_den)
+        out["cpu_baseline"], want_f, want_a = cpu_baseline(wl, oprm)
+        out["cpu_baseline"].update(host_info())
+        out["cpu_baseline_parallel"], want_fs = cpu_baseline_parallel(wl, oprm)
+        # the oracle results the baseline computed are the timed run's parity check
+        parity = {"fsbm_pairs": 0, "acbm_pairs": 0, "blocks_differing": 0}
+        if do_f:
+            for t, wf in enumerate(want_fs):
+                parity["blocks_differing"] += count_mismatches(res_f[t], wf)
+                parity["fsbm_pairs"] += 1
+        if do_a:
+            parity["blocks_differing"] += count_mismatches(res_a[0], want_a)
+            parity["acbm_pairs"] += 1
+        parity["ok"] = parity["blocks_differing"] == 0
+        out["parity"] = parity
+        mismatches = parity["blocks_differing"]
     print(json.dumps(out), flush=True)
+    if mismatches:
+        print(f"bench.py: {mismatches} blocks differ from the oracle", file=sys.stderr)
+        sys.exit(3)
 
 
 if __name__ == "__main__":

@@ -125,6 +125,16 @@ typedef struct acbm_block_stats {
 } acbm_block_stats;
 
 /* ---- library ------------------------------------------------------------ */
+/* The paper's ACBM thresholds for a block size (Section 4 gives alpha =
+ * 1000, beta = 8, gamma = 1/4, tuned for 16x16 macroblocks).  The paper
+ * gives no values for other sizes; because Intra_SAD and SAD both grow with
+ * the pixel count, alpha and beta are scaled by block_w*block_h/256 (integer
+ * division: 250 and 2 for 8x8 blocks); gamma is a ratio of the two and stays
+ * 1/4.  lambda, qp and subpel are copied.  Pure host code: no device is
+ * touched.  Errors: ACBM_E_INVAL for a NULL out or a zero block size. */
+int acbm_default_params(uint32_t block_w, uint32_t block_h, uint32_t lambda, uint32_t qp,
+                        uint32_t subpel, acbm_params* out);
+
 const char* acbm_version(void);
 const char* acbm_strerror(int status);
 /* Detail of the last failing call on this thread ("" if none). */
@@ -281,19 +291,40 @@ int acbm_profile_reset(void);
 int acbm_profile_read(const char* kernel, double* total_ms, uint64_t* launches);
 
 /* ---- serving ------------------------------------------------------------ */
+/* Continuous batching of frame-pair requests over video streams whose
+ * reference frame and motion field stay on the device.  A worker thread
+ * gathers every queued request that can run now -- in submit order, one per
+ * stream at a time (pair t needs pair t-1's frame and field), while the
+ * requests on the GPU stay within max_inflight and the pass's results and
+ * workspace fit in the largest free block of the pool -- into one pass on
+ * one of `lanes` HIP streams: the frame uploads, the batched searches of
+ * acbm_batch (one full-search launch per search class and one resolve for
+ * the FSBM requests, one row-walker launch per block size for the PBM/ACBM
+ * requests), the stored fields and one download of the results.  Requests
+ * that arrive meanwhile join the next pass, and passes on different lanes
+ * overlap on the device.  A request's result equals the *_frame call on
+ * that pair, whatever it was batched with. */
 typedef struct acbm_serve_cfg {
-    size_t   pool_bytes;    /* device memory the server may own (frames, fields, workspace) */
+    size_t   pool_bytes;    /* device memory the server owns (frames, fields, results, workspace) */
     uint32_t max_streams;   /* video streams that can be open at once      */
-    uint32_t max_inflight;  /* requests on the GPU at once                 */
+    uint32_t max_inflight;  /* requests on the GPU at once, over all passes */
     uint32_t queue_depth;   /* requests waiting for admission              */
+    uint32_t lanes;         /* passes in flight at once (HIP streams), 0 = 4, at most 16 */
+    size_t   pinned_bytes;  /* pinned host staging for frames and results, 0 = 512 MiB; frames
+                               take at most three quarters (beyond it they wait in host memory) */
 } acbm_serve_cfg;
 
-typedef struct acbm_serve_stats {
+typedef struct acbm_serve_report {
     uint64_t completed, rejected;
-    double   p50_us, p99_us, mean_us;   /* submit -> result ready            */
-    double   throughput_rps;            /* completed / (last done - first submit) */
-    double   gpu_busy_frac;             /* fraction of that span with work on the GPU */
-} acbm_serve_stats;
+    double   p50_us, p99_us, mean_us;   /* submit -> result ready on the host         */
+    double   throughput_rps;            /* completed / (last done - first submit)     */
+    double   device_busy_frac;          /* union of the passes' device intervals (HIP
+                                           timing events around each pass) over the
+                                           span from the first pass start to the last end */
+    double   device_busy_ms;            /* that union in milliseconds                 */
+    uint64_t passes;                    /* passes completed                           */
+    double   mean_batch;                /* computed requests per pass                 */
+} acbm_serve_report;
 
 typedef struct acbm_server acbm_server;
 
@@ -311,7 +342,10 @@ int acbm_serve_submit(acbm_server* s, uint32_t stream_id, const uint8_t* host_fr
  * timeout_us < 0 waits forever; ACBM_E_TIMEOUT if not ready in time. */
 int acbm_serve_wait(acbm_server* s, uint64_t ticket, acbm_block_result* host_out,
                     int64_t timeout_us);
-int acbm_serve_stats_get(acbm_server* s, acbm_serve_stats* st);
+/* Latency percentiles and throughput of every request completed so far. */
+int acbm_serve_stats(acbm_server* s, acbm_serve_report* st);
+/* The same as acbm_serve_stats (an older name, kept). */
+int acbm_serve_stats_get(acbm_server* s, acbm_serve_report* st);
 int acbm_serve_close(acbm_server* s);
 
 #ifdef __cplusplus

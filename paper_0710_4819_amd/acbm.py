@@ -22,7 +22,9 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libacbm.so")
+# ACBM_LIB names another build of the library (the walker phase-profiling
+# build, libacbm_phases.so); the default is the in-tree libacbm.so.
+LIB_PATH = os.environ.get("ACBM_LIB") or os.path.join(HERE, "libacbm.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "acbm.h")
 
 OK, E_INVAL, E_SHAPE, E_RANGE, E_NOMEM, E_DEVICE, E_BUSY, E_UNSUPPORTED, E_TIMEOUT = \
@@ -59,13 +61,15 @@ class CParams(C.Structure):
 
 class ServeCfg(C.Structure):
     _fields_ = [("pool_bytes", C.c_size_t), ("max_streams", C.c_uint32),
-                ("max_inflight", C.c_uint32), ("queue_depth", C.c_uint32)]
+                ("max_inflight", C.c_uint32), ("queue_depth", C.c_uint32),
+                ("lanes", C.c_uint32), ("pinned_bytes", C.c_size_t)]
 
 
 class ServeStats(C.Structure):
     _fields_ = [("completed", C.c_uint64), ("rejected", C.c_uint64), ("p50_us", C.c_double),
                 ("p99_us", C.c_double), ("mean_us", C.c_double), ("throughput_rps", C.c_double),
-                ("gpu_busy_frac", C.c_double)]
+                ("device_busy_frac", C.c_double), ("device_busy_ms", C.c_double),
+                ("passes", C.c_uint64), ("mean_batch", C.c_double)]
 
 
 class Job(C.Structure):
@@ -91,13 +95,16 @@ class Params:
                        self.subpel)
 
 
-def default_params(block_w: int, block_h: int, lam: int, qp: int | None = None) -> Params:
-    """The paper's thresholds (alpha = 1000, beta = 8, gamma = 1/4, tuned for
-    16x16 macroblocks) with alpha and beta scaled by N*M/256 for other block
-    sizes, since Intra_SAD and SAD grow with the pixel count."""
-    nm = block_w * block_h
-    return Params(lam=lam, qp=lam if qp is None else qp, alpha=1000 * nm // 256,
-                  beta=8 * nm // 256, gamma_num=1, gamma_den=4)
+def default_params(block_w: int, block_h: int, lam: int, qp: int | None = None,
+                   subpel: int = 0) -> Params:
+    """The paper's thresholds for this block size, from the library
+    (acbm_default_params: alpha = 1000, beta = 8, gamma = 1/4 at 16x16,
+    alpha and beta scaled by N*M/256 otherwise).  qp defaults to lambda."""
+    c = CParams()
+    _check(lib().acbm_default_params(block_w, block_h, lam, lam if qp is None else qp, subpel,
+                                     C.byref(c)))
+    return Params(lam=c.lambda_, qp=c.qp, alpha=c.alpha, beta=c.beta, gamma_num=c.gamma_num,
+                  gamma_den=c.gamma_den, subpel=c.subpel)
 
 
 class AcbmError(RuntimeError):
@@ -138,7 +145,9 @@ def lib():
         L.acbm_serve_submit.argtypes = [vp, C.c_uint32, vp, P(Geom), P(CParams), C.c_uint32,
                                         P(C.c_uint64)]
         L.acbm_serve_wait.argtypes = [vp, C.c_uint64, vp, C.c_int64]
+        L.acbm_serve_stats.argtypes = [vp, P(ServeStats)]
         L.acbm_serve_stats_get.argtypes = [vp, P(ServeStats)]
+        L.acbm_default_params.argtypes = [C.c_uint32] * 5 + [P(CParams)]
         L.acbm_serve_close.argtypes = [vp]
         L.acbm_profile_enable.argtypes = [C.c_int]
         L.acbm_profile_read.argtypes = [C.c_char_p, P(C.c_double), P(C.c_uint64)]
@@ -350,12 +359,14 @@ def autotune(block_w: int, block_h: int, p: int, width: int, height: int, pitch:
 
 
 class Server:
-    """Frame-pair motion estimation requests over device-resident streams
-    (acbm_serve).  Frames are host numpy arrays [height, pitch] uint8."""
+    """Frame-pair motion estimation requests over device-resident streams,
+    served by continuous batching (acbm_serve).  Frames are host numpy arrays
+    [height, pitch] uint8."""
 
-    def __init__(self, pool_bytes=4 << 30, max_streams=32, max_inflight=4, queue_depth=256):
+    def __init__(self, pool_bytes=4 << 30, max_streams=32, max_inflight=64, queue_depth=256,
+                 lanes=0, pinned_bytes=0):
         self.h = C.c_void_p()
-        cfg = ServeCfg(pool_bytes, max_streams, max_inflight, queue_depth)
+        cfg = ServeCfg(pool_bytes, max_streams, max_inflight, queue_depth, lanes, pinned_bytes)
         _check(lib().acbm_serve(C.byref(cfg), C.byref(self.h)))
         self.geoms = {}
 
@@ -383,7 +394,7 @@ class Server:
 
     def stats(self) -> dict:
         st = ServeStats()
-        _check(lib().acbm_serve_stats_get(self.h, C.byref(st)))
+        _check(lib().acbm_serve_stats(self.h, C.byref(st)))
         return {k: getattr(st, k) for k, _ in ServeStats._fields_}
 
     def close(self):
@@ -405,6 +416,21 @@ def profile_read(kernel: str) -> tuple[float, int]:
     ms, n = C.c_double(), C.c_uint64()
     _check(lib().acbm_profile_read(kernel.encode(), C.byref(ms), C.byref(n)))
     return ms.value, n.value
+
+
+PHASE_NAMES = ("blocks", "critical_blocks", "dependency_wait", "phase_a", "phase_b", "phase_c",
+               "critical_search", "row_setup")
+
+
+def phase_profile_read(reset: bool = False) -> dict | None:
+    """Walker phase totals (the profiling build only, else None): block
+    counts and summed s_memrealtime ticks (100 MHz) per phase."""
+    L = lib()
+    if not hasattr(L, "acbm_phase_profile_read"):
+        return None
+    out = (C.c_uint64 * 8)()
+    _check(L.acbm_phase_profile_read(out, 1 if reset else 0))
+    return dict(zip(PHASE_NAMES, list(out)))
 
 
 def to_numpy(res: torch.Tensor) -> np.ndarray:

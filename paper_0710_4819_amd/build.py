@@ -23,9 +23,12 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-I", os.path.join(ROOT, "include")]
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+PHASES_LIB = os.path.join(HERE, "libacbm_phases.so")
+
+
+def _compile(src: str, verbose: bool, build_dir: str = BUILD, extra=()) -> str:
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     p = subprocess.run(cmd, capture_output=True, text=True)
@@ -37,40 +40,25 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, jobs: int = 8, phases: bool = False) -> str:
+    """libacbm.so; with phases=True the walker phase-profiling build
+    libacbm_phases.so instead (ACBM_PHASE_PROFILE: the row walkers time their
+    phases; results are the same, times are a little longer)."""
+    build_dir = BUILD + ("_phases" if phases else "")
+    lib = PHASES_LIB if phases else LIB
+    extra = ("-DACBM_PHASE_PROFILE",) if phases else ()
+    os.makedirs(build_dir, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
-    tmp = LIB + ".tmp%d" % os.getpid()
+        objs = list(ex.map(lambda s: _compile(s, verbose, build_dir, extra), srcs))
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
-
-
-PROBE_SRC = os.path.join(HERE, "probe", "probe_sad.hip")
-PROBE_BIN = os.path.join(HERE, "probe", "probe_sad")
-
-
-def build_probe(verbose: bool = False) -> str:
-    """The SAD-instruction probe (semantics and issue rate), a standalone
-    executable next to its source."""
-    tmp = PROBE_BIN + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature", "-Xclang",
-           "-packed-fp32-ops", PROBE_SRC, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    p = subprocess.run(cmd, capture_output=True, text=True)
-    if p.returncode != 0:
-        raise RuntimeError(f"hipcc failed on the probe:\n{p.stderr}")
-    os.replace(tmp, PROBE_BIN)
-    return PROBE_BIN
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
-    build_probe(verbose="-v" in sys.argv)
-    print(LIB)
+    print(build(verbose="-v" in sys.argv, phases="--phases" in sys.argv))

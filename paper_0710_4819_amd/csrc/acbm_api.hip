@@ -183,6 +183,53 @@ SearchPlan plan_search_model(int N, int M, int p, int R) {
 namespace {
 std::mutex g_tuned_mu;
 std::map<std::tuple<int, int, int>, SearchPlan> g_tuned;
+// Plans read from the tuning cache, with the time per pair they were
+// measured at (acbm_autotune returns these without timing again).
+std::map<std::tuple<int, int, int>, float> g_cached_ms;
+bool g_cache_loaded = false;
+
+// Architecture name of the current device without its feature suffix
+// ("gfx950" of "gfx950:sramecc+:xnack-").
+std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return "";
+  std::string a = prop.gcnArchName;
+  return a.substr(0, a.find(':'));
+}
+
+// The tuning cache named by ACBM_TUNE_CACHE: one JSON object per line,
+// {"arch": "gfx950", "N": 16, "M": 16, "p": 32, "R": 6, "ms_per_pair": 0.0887},
+// appended by acbm_autotune; a later line for the same key wins.  Lines of
+// another architecture or with a plan that no longer fits are ignored.
+// g_tuned_mu is held.
+void load_tune_cache_locked() {
+  if (g_cache_loaded) return;
+  g_cache_loaded = true;
+  const char* path = std::getenv("ACBM_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  const std::string arch = device_arch();
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    char a[64];
+    int N = 0, M = 0, p = 0, R = 0;
+    float ms = 0;
+    if (std::sscanf(line, " { \"arch\" : \"%63[^\"]\" , \"N\" : %d , \"M\" : %d , \"p\" : %d , "
+                          "\"R\" : %d , \"ms_per_pair\" : %f",
+                    a, &N, &M, &p, &R, &ms) != 6 ||
+        arch != a)
+      continue;
+    if ((N != 8 && N != 16) || (M != 8 && M != 16) || p < 0 || p > 127) continue;
+    const SearchPlan pl = plan_search_model(N, M, p, R);
+    if (!pl.R) continue;
+    g_tuned[std::make_tuple(N, M, p)] = pl;
+    g_cached_ms[std::make_tuple(N, M, p)] = ms;
+  }
+  std::fclose(f);
+}
 }  // namespace
 
 void set_tuned_plan(int N, int M, int p, const SearchPlan& pl) {
@@ -190,10 +237,36 @@ void set_tuned_plan(int N, int M, int p, const SearchPlan& pl) {
   g_tuned[std::make_tuple(N, M, p)] = pl;
 }
 
+bool cached_plan(int N, int M, int p, SearchPlan* pl, float* ms) {
+  std::lock_guard<std::mutex> lk(g_tuned_mu);
+  load_tune_cache_locked();
+  auto it = g_cached_ms.find(std::make_tuple(N, M, p));
+  if (it == g_cached_ms.end()) return false;
+  *pl = g_tuned[it->first];
+  *ms = it->second;
+  return true;
+}
+
+void save_tuned_plan(int N, int M, int p, const SearchPlan& pl, float ms) {
+  std::lock_guard<std::mutex> lk(g_tuned_mu);
+  load_tune_cache_locked();
+  g_tuned[std::make_tuple(N, M, p)] = pl;
+  const char* path = std::getenv("ACBM_TUNE_CACHE");
+  if (!path || !*path) return;
+  g_cached_ms[std::make_tuple(N, M, p)] = ms;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;  // an unwritable cache only costs the next process a re-tune
+  std::fprintf(f, "{\"arch\": \"%s\", \"N\": %d, \"M\": %d, \"p\": %d, \"R\": %d, "
+                  "\"ms_per_pair\": %.6f}\n",
+               device_arch().c_str(), N, M, p, pl.R, ms);
+  std::fclose(f);
+}
+
 SearchPlan plan_search(int N, int M, int p, int max_threads) {
   const char* force = std::getenv("ACBM_R");
   if (!force && max_threads >= 1024) {
     std::lock_guard<std::mutex> lk(g_tuned_mu);
+    load_tune_cache_locked();
     auto it = g_tuned.find(std::make_tuple(N, M, p));
     if (it != g_tuned.end()) return it->second;
   }
@@ -235,6 +308,25 @@ const char* acbm_strerror(int s) {
 }
 
 const char* acbm_last_error(void) { return t_last_error.c_str(); }
+
+int acbm_default_params(uint32_t block_w, uint32_t block_h, uint32_t lambda, uint32_t qp,
+                        uint32_t subpel, acbm_params* out) {
+  if (!out) return fail(ACBM_E_INVAL, "out is NULL");
+  if (!block_w || !block_h) return fail(ACBM_E_INVAL, "zero block size");
+  // Section 4's values for 16x16; alpha and beta scale with the pixel count
+  const uint64_t nm = (uint64_t)block_w * block_h;
+  const uint64_t alpha = 1000 * nm / 256, beta = 8 * nm / 256;
+  if (alpha > 0xFFFFFFFFull || beta > 0xFFFFFFFFull)
+    return fail(ACBM_E_RANGE, "block too large for the scaled thresholds");
+  out->lambda = lambda;
+  out->qp = qp;
+  out->alpha = (uint32_t)alpha;
+  out->beta = (uint32_t)beta;
+  out->gamma_num = 1;
+  out->gamma_den = 4;
+  out->subpel = subpel;
+  return ACBM_OK;
+}
 
 int acbm_init(void) {
   t_last_error.clear();

@@ -210,8 +210,8 @@ __global__ void k_put_table(uint64_t* __restrict__ dst, const TableChunk c, int 
 
 // Fills the device pointers of the plan, plans the walker groups and
 // enqueues the table writes.
-int write_tables(const acbm_job* jobs, Plan* pl, std::vector<PredGroupPlan>* gplans, char* ws,
-                 hipStream_t st) {
+int write_tables(const acbm_job* jobs, const acbm_mv* const* prev0, Plan* pl,
+                 std::vector<PredGroupPlan>* gplans, char* ws, hipStream_t st) {
   if (!pl->table_bytes) return ACBM_OK;
   char* table = ws + pl->table_off;
   std::vector<uint64_t> host(pl->table_bytes / 8, 0);
@@ -252,6 +252,10 @@ int write_tables(const acbm_job* jobs, Plan* pl, std::vector<PredGroupPlan>* gpl
       a.words = reinterpret_cast<uint32_t*>(ws + pl->slice[pg.job_index[n]]);
       a.frames = reinterpret_cast<const uint8_t* const*>(table + pg.off_ptrs + pp * sizeof(void*));
       a.out = j.out;
+      if (prev0 && prev0[pg.job_index[n]]) {  // the job's first pair has a temporal field
+        a.prev0 = reinterpret_cast<const uint8_t*>(prev0[pg.job_index[n]]);
+        a.prev0_stride = sizeof(acbm_mv);
+      }
       std::memcpy(hb + pg.off_ptrs + pp * sizeof(void*), j.frames, j.nframes * sizeof(void*));
       pp += j.nframes;
       std::memcpy(hb + pg.off_args + n * sizeof(PredArgs), &a, sizeof(PredArgs));
@@ -378,13 +382,23 @@ namespace {
 // finally waits for the side streams.  Kernels and stream-ordering events
 // only, so the sequence can be recorded into a graph as it is (the side
 // streams become parallel branches).
-int enqueue_batch(const acbm_job* jobs, size_t njobs, void* ws, hipStream_t st) {
+int enqueue_batch(const acbm_job* jobs, size_t njobs, const acbm_mv* const* prev0, void* ws,
+                  hipStream_t st, bool allow_side, std::vector<const uint32_t*>* status_words) {
   Plan pl;
   int rc = make_plan(jobs, njobs, &pl);
   if (rc) return rc;
   char* base = static_cast<char*>(ws);
   std::vector<PredGroupPlan> gplans;
-  if ((rc = write_tables(jobs, &pl, &gplans, base, st))) return rc;
+  if ((rc = write_tables(jobs, prev0, &pl, &gplans, base, st))) return rc;
+  if (status_words) {
+    status_words->clear();
+    for (const PGroup& pg : pl.pgroups)
+      status_words->push_back(reinterpret_cast<const uint32_t*>(
+          base + pl.scratch_off + pg.off_hdr + offsetof(WsHeader, status)));
+    for (size_t i : pl.predictive)
+      status_words->push_back(
+          reinterpret_cast<const uint32_t*>(base + pl.slice[i] + offsetof(WsHeader, status)));
+  }
   const BatchJob* all = reinterpret_cast<const BatchJob*>(base + pl.table_off + pl.off_jobs);
 
   // Walker launches: the groups, then the jobs that run alone, round robin
@@ -397,7 +411,8 @@ int enqueue_batch(const acbm_job* jobs, size_t njobs, void* ws, hipStream_t st) 
   std::unique_lock<std::mutex> lk(g_side_mu, std::defer_lock);
   SidePool* sp = nullptr;
   int nside = 0;
-  const int want = std::min<int>(side_streams(), (int)std::min<size_t>(kSideStreams, off_st));
+  int want = allow_side ? std::min<int>(side_streams(), (int)std::min<size_t>(kSideStreams, off_st))
+                        : 0;
   if (want > 0) {
     int cur = -1;
     hipDevice_t sdev = -1;
@@ -405,14 +420,40 @@ int enqueue_batch(const acbm_job* jobs, size_t njobs, void* ws, hipStream_t st) 
         sdev == cur) {
       lk.lock();
       if ((rc = side_pool(cur, &sp))) return rc;
-      hipError_t e = hipEventRecord(sp->fork, st);
-      if (e != hipSuccess) return hip_fail(e, "forking the batch's side streams");
-      for (; nside < want; ++nside)
-        if ((e = hipStreamWaitEvent(sp->s[nside], sp->fork, 0)) != hipSuccess) {
-          rc = hip_fail(e, "forking the batch's side streams");
-          break;
-        }
+      // A side stream forked into a capture stays in it until that capture
+      // ends, which another thread may not have done yet.  Fork only onto
+      // side streams that are idle or already in the capture `st` is in;
+      // otherwise keep every launch on `st`.
+      hipStreamCaptureStatus ost = hipStreamCaptureStatusNone;
+      unsigned long long oid = 0;
+      hipError_t e = hipStreamGetCaptureInfo(st, &ost, &oid);
+      if (e != hipSuccess) return hip_fail(e, "querying the stream's capture state");
+      bool usable = true;
+      for (int i = 0; i < want && usable; ++i) {
+        hipStreamCaptureStatus sst = hipStreamCaptureStatusNone;
+        unsigned long long sid = 0;
+        e = hipStreamGetCaptureInfo(sp->s[i], &sst, &sid);
+        if (e != hipSuccess) return hip_fail(e, "querying a side stream's capture state");
+        if (sst != hipStreamCaptureStatusNone &&
+            !(sst == hipStreamCaptureStatusActive && ost == hipStreamCaptureStatusActive &&
+              sid == oid))
+          usable = false;
+      }
+      if (!usable) {
+        lk.unlock();
+        sp = nullptr;
+        want = 0;
+      }
     }
+  }
+  if (want > 0 && sp) {
+    hipError_t e = hipEventRecord(sp->fork, st);
+    if (e != hipSuccess) return hip_fail(e, "forking the batch's side streams");
+    for (; nside < want; ++nside)
+      if ((e = hipStreamWaitEvent(sp->s[nside], sp->fork, 0)) != hipSuccess) {
+        rc = hip_fail(e, "forking the batch's side streams");
+        break;
+      }
   }
   const int lanes = nside + (has_fsbm && nside ? 0 : 1);  // lane nside is `st`
   for (size_t u = 0; u < nunits && !rc; ++u) {
@@ -433,8 +474,8 @@ int enqueue_batch(const acbm_job* jobs, size_t njobs, void* ws, hipStream_t st) 
       check_geom(&j.geom, &k);
       size_t b = 0;
       job_ws(j, &b);
-      rc = launch_predictive(k, j.params, (int)j.algo, j.frames, j.nframes - 1, nullptr,
-                             base + pl.slice[i], b, j.out, su);
+      rc = launch_predictive(k, j.params, (int)j.algo, j.frames, j.nframes - 1,
+                             prev0 ? prev0[i] : nullptr, base + pl.slice[i], b, j.out, su);
     }
   }
   if (!rc) rc = enqueue_fsbm(jobs, pl, base, all, st);
@@ -499,6 +540,18 @@ int enqueue_fsbm(const acbm_job* jobs, const Plan& pl, char* base, const BatchJo
 
 }  // namespace
 
+// A validated batch whose PBM/ACBM jobs may start from a temporal field
+// (prev0[i], acbm_mv per block, or null for zeros), enqueued on `st` alone
+// or with side streams; status_words receives the device addresses of the
+// walker launches' status words.
+int acbm::batch_enqueue(const acbm_job* jobs, size_t njobs, const acbm_mv* const* prev0,
+                        void* ws, size_t ws_bytes, hipStream_t st, bool side_streams,
+                        std::vector<const uint32_t*>* status_words) {
+  int rc = validate_jobs(jobs, njobs, ws, ws_bytes);
+  if (rc) return rc;
+  return enqueue_batch(jobs, njobs, prev0, ws, st, side_streams, status_words);
+}
+
 struct acbm_batch_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -513,7 +566,7 @@ extern "C" {
 int acbm_batch(const acbm_job* jobs, size_t njobs, void* ws, size_t ws_bytes, void* stream) {
   int rc = validate_jobs(jobs, njobs, ws, ws_bytes);
   if (rc) return rc;
-  return enqueue_batch(jobs, njobs, ws, static_cast<hipStream_t>(stream));
+  return enqueue_batch(jobs, njobs, nullptr, ws, static_cast<hipStream_t>(stream), true, nullptr);
 }
 
 int acbm_batch_graph_create(const acbm_job* jobs, size_t njobs, void* ws, size_t ws_bytes,
@@ -530,7 +583,7 @@ int acbm_batch_graph_create(const acbm_job* jobs, size_t njobs, void* ws, size_t
     (void)hipStreamDestroy(st);
     return hip_fail(e, "beginning the batch capture");
   }
-  rc = enqueue_batch(jobs, njobs, ws, st);
+  rc = enqueue_batch(jobs, njobs, nullptr, ws, st, true, nullptr);
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(st, &graph);
   (void)hipStreamDestroy(st);

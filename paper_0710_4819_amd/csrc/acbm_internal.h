@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/acbm.h"
 
@@ -109,6 +110,11 @@ SearchPlan plan_search(int N, int M, int p, int max_threads = 1024);
 SearchPlan plan_search_model(int N, int M, int p, int R);
 // Records a measured plan for (N, M, p); plan_search returns it from then on.
 void set_tuned_plan(int N, int M, int p, const SearchPlan& pl);
+// The same, also appended to the tuning cache file (ACBM_TUNE_CACHE) with its
+// measured time per pair, when that variable names one.
+void save_tuned_plan(int N, int M, int p, const SearchPlan& pl, float ms);
+// A plan for (N, M, p) read from the tuning cache file, with its time.
+bool cached_plan(int N, int M, int p, SearchPlan* pl, float* ms);
 
 // Brackets one kernel launch with timing events when profiling is on
 // (acbm_profile_enable); a no-op otherwise.
@@ -156,6 +162,13 @@ int launch_search_batch(int N, int M, const SearchPlan& pl, size_t lds, const Ba
                         int njobs, uint32_t items, hipStream_t s);
 // Creates the current device's side streams for batch walker launches.
 int batch_side_streams_init();
+// acbm_batch with a temporal field for the first pair of each PBM/ACBM job
+// (prev0[i], may be null; prev0 itself may be null) and the choice of side
+// streams; status_words (may be null) receives the device addresses of the
+// status words of its walker launches (0 = every block finished).
+int batch_enqueue(const acbm_job* jobs, size_t njobs, const acbm_mv* const* prev0, void* ws,
+                  size_t ws_bytes, hipStream_t st, bool side_streams,
+                  std::vector<const uint32_t*>* status_words);
 int launch_resolve_batch(const BatchJob* jobs, int njobs, uint32_t pairs, size_t lds,
                          hipStream_t s);
 size_t predictive_ws_bytes(const KGeom& g, uint32_t npairs);

@@ -54,6 +54,19 @@ constexpr uint32_t kSpinLimit = 1u << 22;  // polls before a dependency wait giv
 #define ACBM_PRED_WAVES 3  // waves per SIMD the register budget must allow
 #endif
 
+// Per-phase device time of the row walkers, in a build with
+// ACBM_PHASE_PROFILE defined (libacbm_phases.so; never the product
+// library): thread 0 of every walker stamps s_memrealtime (100 MHz) at the
+// phase boundaries of each block and adds its totals here when it leaves.
+// [0] blocks, [1] critical blocks, [2] dependency wait (wave 0), [3] phase A
+// without the wait, [4] B, [5] C, [6] D (critical search), [7] row set-up.
+#ifdef ACBM_PHASE_PROFILE
+__device__ unsigned long long g_phase[8];
+#define ACBM_PH(...) __VA_ARGS__
+#else
+#define ACBM_PH(...)
+#endif
+
 // Rows (t, r) with r + 2t = k.
 __host__ __device__ inline int row_tlo(int k, int by) { return max(0, (k - (by - 1) + 1) / 2); }
 __host__ __device__ inline int row_thi(int k, int npairs) { return min(npairs - 1, k / 2); }
@@ -494,8 +507,10 @@ k_predictive(const PredArgs* __restrict__ jobs, const uint32_t* __restrict__ ord
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int f = (int)threadIdx.x - 64, nf = NT - 64;  // fetching lanes: waves 1..
+  ACBM_PH(uint64_t ph[8] = {0, 0, 0, 0, 0, 0, 0, 0}; uint64_t ph_t0 = 0, ph_tw = 0;)
 
   for (;;) {
+    ACBM_PH(const uint64_t ph_row = __builtin_amdgcn_s_memrealtime();)
     if (threadIdx.x == 0) {
       const uint32_t tk = atomicAdd(&hdr->ticket, 1u);
       sh_row = tk < total_rows ? order[tk] : 0xFFFFFFFFu;
@@ -505,7 +520,10 @@ k_predictive(const PredArgs* __restrict__ jobs, const uint32_t* __restrict__ ord
     // LDS words are uniform; readfirstlane lets the compiler see that, so the
     // exits of this loop (which contains barriers) stay uniform branches
     const uint32_t rw = __builtin_amdgcn_readfirstlane(sh_row);
-    if (rw == 0xFFFFFFFFu || __builtin_amdgcn_readfirstlane(sh_abort)) return;
+    if (rw == 0xFFFFFFFFu || __builtin_amdgcn_readfirstlane(sh_abort)) {
+      ACBM_PH(if (threadIdx.x == 0) for (int k = 0; k < 8; ++k) atomicAdd(&g_phase[k], ph[k]);)
+      return;
+    }
     const PredArgs& a = jobs[rw >> 24];
     const int t = (int)((rw >> 12) & 0xFFFu);
     const int r = (int)(rw & 0xFFFu);
@@ -532,8 +550,10 @@ k_predictive(const PredArgs* __restrict__ jobs, const uint32_t* __restrict__ ord
       pre_word = d0 ? load_word(d0) : 0u;
     }
     __syncthreads();
+    ACBM_PH(if (threadIdx.x == 0) ph[7] += __builtin_amdgcn_s_memrealtime() - ph_row;)
 
     for (int c = 0; c < bx; ++c) {
+      ACBM_PH(if (threadIdx.x == 0) ph_t0 = __builtin_amdgcn_s_memrealtime();)
       const int cb = c & 1;
       const uint32_t* cd = curd[cb];
       const int b = r * bx + c;
@@ -582,6 +602,7 @@ k_predictive(const PredArgs* __restrict__ jobs, const uint32_t* __restrict__ ord
           }
           __builtin_amdgcn_s_sleep(2);
         }
+        ACBM_PH(if (lane == 0) { ph_tw = __builtin_amdgcn_s_memrealtime(); ph[2] += ph_tw - ph_t0; })
         if (dw) val = (uint16_t)(word & 0xFFFFu);
         if (more) {
           const uint32_t* wn = dep_word(a, words, lane, t, r, c + 1);
@@ -644,6 +665,7 @@ k_predictive(const PredArgs* __restrict__ jobs, const uint32_t* __restrict__ ord
         }
       }
       __syncthreads();
+      ACBM_PH(uint64_t ph_t1 = 0; if (threadIdx.x == 0) { ph_t1 = __builtin_amdgcn_s_memrealtime(); ph[3] += ph_t1 - ph_tw; })
       if (__builtin_amdgcn_readfirstlane(sh_abort)) return;
       const int px = __builtin_amdgcn_readfirstlane(sh_px);
       const int py = __builtin_amdgcn_readfirstlane(sh_py);
@@ -663,6 +685,7 @@ k_predictive(const PredArgs* __restrict__ jobs, const uint32_t* __restrict__ ord
       else
         pbm_neighbourhoods<N, M, NT>(ring, w, cb0, cd, cu, cv, np, nbr);
       __syncthreads();
+      ACBM_PH(uint64_t ph_t2 = 0; if (threadIdx.x == 0) { ph_t2 = __builtin_amdgcn_s_memrealtime(); ph[4] += ph_t2 - ph_t1; })
 
       // ---- C: PBM steps 2 and 3, ACBM decision (every wave, redundantly, so
       //         that no barrier is needed to share it) -----------------------
@@ -728,6 +751,7 @@ k_predictive(const PredArgs* __restrict__ jobs, const uint32_t* __restrict__ ord
         }
       }
 
+      ACBM_PH(uint64_t ph_t3 = 0; if (threadIdx.x == 0) { ph_t3 = __builtin_amdgcn_s_memrealtime(); ph[5] += ph_t3 - ph_t2; ph[0] += 1; })
       // ---- D: critical block: full search with the same predictor ---------
       if (crit_n) {  // uniform: every wave took the same decision
         const ValidBox vbox = valid_box(p, x0, y0, N, M, g.width, g.height);
@@ -764,6 +788,7 @@ k_predictive(const PredArgs* __restrict__ jobs, const uint32_t* __restrict__ ord
           write_result(a.out + (size_t)t * nb + b, words + b, u, v, (uint32_t)(best >> 32), rate,
                        a.lam, cands, ACBM_MODE_CRITICAL, intra);
           sh_left = pack_mv(u, v);
+          ACBM_PH(ph[6] += __builtin_amdgcn_s_memrealtime() - ph_t3; ph[1] += 1;)
         }
       }
 
@@ -999,6 +1024,21 @@ int launch_predictive_group(int bw, int bh, bool hp, const PredGroupPlan& pl,
   if (bw == 8 && bh == 16) return launch_pred_nm<8, 16>(L, pl.R, pl.threads, hp, st);
   return launch_pred_nm<8, 8>(L, pl.R, pl.threads, hp, st);
 }
+
+#ifdef ACBM_PHASE_PROFILE
+// Reads (and with reset != 0 clears) the walkers' phase totals; exported by
+// the profiling build only.
+extern "C" int acbm_phase_profile_read(uint64_t* out8, int reset) {
+  if (!out8) return fail(ACBM_E_INVAL, "out is NULL");
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpyFromSymbol(out8, HIP_SYMBOL(g_phase), 8 * sizeof(uint64_t));
+  if (e == hipSuccess && reset) {
+    const uint64_t zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    e = hipMemcpyToSymbol(HIP_SYMBOL(g_phase), zero, sizeof(zero));
+  }
+  return e == hipSuccess ? ACBM_OK : hip_fail(e, "reading the phase profile");
+}
+#endif
 
 int launch_predictive(const KGeom& g, const acbm_params& prm, int algo,
                       const uint8_t* const* frames, uint32_t npairs, const acbm_mv* prev_field,

@@ -4,7 +4,9 @@
 // exactly (LDS bank conflicts, occupancy and the epilogue vary with R and
 // p); acbm_autotune times every candidate on the device instead and records
 // the fastest.  The search result never depends on R (every plan computes
-// the same exact SADs), so tuning only moves time.
+// the same exact SADs), so tuning only moves time.  With ACBM_TUNE_CACHE
+// naming a file, each measured plan is appended to it and later processes
+// take it from there instead of timing again.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -51,6 +53,14 @@ extern "C" int acbm_autotune(const acbm_geom* g, uint32_t* best_rows, float* bes
   int rc = check_geom(g, &k);
   if (rc) return rc;
   if ((rc = check_device())) return rc;
+  SearchPlan cached{0, 0, 0};
+  float cached_ms = 0;
+  if (cached_plan(k.bw, k.bh, k.p, &cached, &cached_ms)) {
+    // measured by an earlier process on this architecture: reuse it
+    if (best_rows) *best_rows = (uint32_t)cached.R;
+    if (best_ms) *best_ms = cached_ms;
+    return ACBM_OK;
+  }
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t fb = align256((size_t)k.pitch * k.height);
   const size_t wsb = fsbm_ws_bytes(k, 1);
@@ -90,7 +100,7 @@ extern "C" int acbm_autotune(const acbm_geom* g, uint32_t* best_rows, float* bes
     }
   }
   if (!best.R) return fail(ACBM_E_UNSUPPORTED, "search window does not fit in LDS");
-  set_tuned_plan(k.bw, k.bh, k.p, best);
+  save_tuned_plan(k.bw, k.bh, k.p, best, best_t);
   if (best_rows) *best_rows = (uint32_t)best.R;
   if (best_ms) *best_ms = best_t;
   return ACBM_OK;

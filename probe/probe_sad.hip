@@ -8,8 +8,12 @@
 //    grid; the time per instruction is compared with V_ALIGNBYTE_B32 (a
 //    full-rate op) run the same way, which gives the issue cost independent
 //    of the clock.
+// 3. Clock: the shader clock while a full grid runs a dependent full-rate
+//    chain, from the cycle counter (s_memtime) against the constant-rate
+//    wall clock (s_memrealtime), per workgroup, reported as min/median/max.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstdint>
 #include <cstdio>
@@ -85,6 +89,28 @@ __global__ void __launch_bounds__(256) k_rate_add(uint32_t* out, uint32_t seed) 
 #pragma unroll
   for (int k = 0; k < 8; ++k) s ^= acc[k];
   out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+// Thread 0 of every workgroup stamps both counters around a dependent chain
+// of full-rate ops; stamps[4*b .. 4*b+3] = cycles0, wall0, cycles1, wall1.
+__global__ void __launch_bounds__(256) k_clock(uint64_t* stamps, uint32_t* sink, uint32_t seed) {
+  __syncthreads();
+  uint64_t c0 = 0, w0 = 0;
+  if (threadIdx.x == 0) {
+    c0 = clock64();
+    w0 = wall_clock64();
+  }
+  uint32_t acc = threadIdx.x ^ seed;
+  for (int it = 0; it < 64 * kIters; ++it) acc = __builtin_amdgcn_alignbyte(acc, acc + it, 1u);
+  sink[blockIdx.x * blockDim.x + threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t c1 = clock64(), w1 = wall_clock64();
+    stamps[4 * blockIdx.x + 0] = c0;
+    stamps[4 * blockIdx.x + 1] = w0;
+    stamps[4 * blockIdx.x + 2] = c1;
+    stamps[4 * blockIdx.x + 3] = w1;
+  }
 }
 
 static uint64_t model_qsad(uint64_t a, uint32_t b, uint64_t c, bool clamp) {
@@ -205,5 +231,28 @@ int main() {
               ops / t_qsad / 1e9, 16 * ops / t_qsad / 1e9);
   std::printf("  issue cost relative to a full-rate op: sad_u8 %.2f, qsad %.2f\n",
               t_sad / t_add, t_qsad / t_add);
+
+  // ---- clock ----
+  int wall_khz = 0;
+  CHECK(hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, 0));
+  uint64_t* dstamps;
+  CHECK(hipMalloc(&dstamps, (size_t)grid * 4 * 8));
+  hipLaunchKernelGGL(k_clock, dim3(grid), dim3(256), 0, 0, dstamps, (uint32_t*)out, 1u);
+  CHECK(hipDeviceSynchronize());
+  hipLaunchKernelGGL(k_clock, dim3(grid), dim3(256), 0, 0, dstamps, (uint32_t*)out, 2u);
+  CHECK(hipDeviceSynchronize());
+  std::vector<uint64_t> st((size_t)grid * 4);
+  CHECK(hipMemcpy(st.data(), dstamps, st.size() * 8, hipMemcpyDeviceToHost));
+  std::vector<double> mhz;
+  for (int b = 0; b < grid; ++b) {
+    double cyc = (double)(st[4 * b + 2] - st[4 * b + 0]);
+    double wall = (double)(st[4 * b + 3] - st[4 * b + 1]);
+    if (wall > 0) mhz.push_back(cyc / wall * wall_khz / 1e3);
+  }
+  std::sort(mhz.begin(), mhz.end());
+  if (!mhz.empty())
+    std::printf("clock (cycle counter / %d kHz wall clock, %zu workgroups): min %.0f, median %.0f, "
+                "max %.0f MHz\n", wall_khz, mhz.size(), mhz.front(), mhz[mhz.size() / 2],
+                mhz.back());
   return 0;
 }

@@ -126,8 +126,16 @@ def test_batch_workspace_grows_with_walker_groups():
 
 
 def test_default_params_scale_with_block_size():
+    """acbm_default_params: Section 4's alpha, beta, gamma at 16x16, alpha and
+    beta scaled by N*M/256 for other sizes, computed by the C library."""
     assert acbm.default_params(16, 16, 8) == acbm.Params(8, 8, 1000, 8, 1, 4)
     assert acbm.default_params(8, 8, 8) == acbm.Params(8, 8, 250, 2, 1, 4)
+    assert acbm.default_params(16, 8, 8, qp=5) == acbm.Params(8, 5, 500, 4, 1, 4)
+    assert acbm.default_params(16, 16, 2, subpel=1).subpel == 1
+    L = acbm.lib()
+    assert L.acbm_default_params(16, 16, 8, 8, 0, None) == acbm.E_INVAL
+    c = acbm.CParams()
+    assert L.acbm_default_params(0, 16, 8, 8, 0, C.byref(c)) == acbm.E_INVAL
 
 
 def test_stats_and_precision_argument_errors():

@@ -214,3 +214,56 @@ def test_global_mode_capture_after_init():
     for i in (0, 1):
         frames, bw, bh, p, algo, prm = jobs[i]
         assert_oracle(f"job {i}", eager[i], frames, bw, bh, p, prm, algo)
+
+
+def test_eager_batch_beside_an_open_capture():
+    """While one thread holds a capture open whose batch forked onto the
+    library's side streams, another thread's eager acbm_batch must not fork
+    onto those streams (they stay in the capture until it ends): it runs on
+    its own stream, completes and matches the eager results; the capture then
+    replays correctly."""
+    import threading
+    dev = torch.device("cuda", 0)
+    assert acbm.lib().acbm_init() == 0
+    jobs = _walker_jobs()[:4]
+    b1, b2 = _batch(dev, jobs), _batch(dev, jobs)
+    ws1 = torch.empty(max(256, b1.workspace_size()), dtype=torch.uint8, device=dev)
+    ws2 = torch.empty(max(256, b2.workspace_size()), dtype=torch.uint8, device=dev)
+    eager = [acbm.to_numpy(o.clone()) for o in b1.run(ws1)]
+    torch.cuda.synchronize()
+    assert b1.status(ws1) == 0
+    s1, s2 = torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)
+    got = {}
+
+    def other():
+        try:
+            with torch.cuda.stream(s2):
+                for o in b2.outs:
+                    o.fill_(0x77)
+                b2.run(ws2, s2)
+                s2.synchronize()
+                got["status"] = b2.status(ws2, s2)
+                got["outs"] = [acbm.to_numpy(o) for o in b2.outs]
+        except Exception as e:  # reported by the main thread
+            got["error"] = e
+
+    g = torch.cuda.CUDAGraph()
+    say("capture open on one thread, eager batch on another")
+    with torch.cuda.graph(g, stream=s1, capture_error_mode="thread_local"):
+        b1.run(ws1, s1)
+        t = threading.Thread(target=other)
+        t.start()
+        t.join()
+    assert "error" not in got, got.get("error")
+    assert got["status"] == 0
+    for i, o in enumerate(got["outs"]):
+        assert np.array_equal(o, eager[i]), f"eager batch beside the capture, job {i}"
+    for rep in range(2):
+        for o in b1.outs:
+            o.fill_(0x3C)
+        say(f"replay {rep} of the capture")
+        g.replay()
+        torch.cuda.synchronize()
+        for i, o in enumerate(b1.outs):
+            assert np.array_equal(acbm.to_numpy(o), eager[i]), f"replay {rep}, job {i}"
+    assert b1.status(ws1) == 0

@@ -1,5 +1,7 @@
-"""Served requests: each result equals the same frame pair run alone, however
-requests of different streams interleave on the GPU, and error paths."""
+"""Served requests (continuous batching): each result equals the same frame
+pair run alone, however requests of different streams are gathered into
+passes and however the passes overlap on the GPU; streams at p = 64 against
+the oracle; error paths."""
 import dataclasses
 
 import numpy as np
@@ -27,6 +29,11 @@ def _streams():
         ([f[32:176, 16:192].copy() for f in sc.frames], 16, 9, 2, acbm.ALGO_ACBM),
         # half-pel precision (vectors and the stream's resident field in half-pel units)
         ([f[:144, :176].copy() for f in sc.frames], 16, 7, 8, ("half", acbm.ALGO_ACBM)),
+        # p = 64, the largest served search range
+        (synth.stream_frames({"stream": 0, "width": 640, "height": 480, "p": 64,
+                              "seed": 5400}, 3), 16, 64, 8, acbm.ALGO_ACBM),
+        (synth.stream_frames({"stream": 1, "width": 640, "height": 480, "p": 64,
+                              "seed": 5401}, 3), 16, 64, 8, acbm.ALGO_FSBM),
     ]
 
 
@@ -43,9 +50,15 @@ def _alone(frames, blk, p, prm, algo):
     return acbm.to_numpy(b.run()[0])
 
 
-def test_served_results_equal_alone_in_a_mix():
+@pytest.mark.parametrize("lanes,max_inflight", [(4, 64), (2, 3), (1, 64)])
+def test_served_results_equal_alone_in_a_mix(lanes, max_inflight):
+    """Every frame of every stream submitted up front, streams interleaved:
+    the worker gathers several streams into each pass.  lanes and
+    max_inflight change how requests are batched and overlapped, never the
+    results."""
     streams = _streams()
-    srv = acbm.Server(pool_bytes=2 << 30, max_streams=8, max_inflight=3, queue_depth=64)
+    srv = acbm.Server(pool_bytes=2 << 30, max_streams=8, max_inflight=max_inflight,
+                      queue_depth=64, lanes=lanes)
     try:
         tickets = {}
         nmax = max(len(s[0]) for s in streams)
@@ -65,8 +78,8 @@ def test_served_results_equal_alone_in_a_mix():
         alone = _alone(frames, blk, p, prm, a)
         for t in range(1, len(frames)):
             assert np.array_equal(got[(sid, t)], alone[t - 1]), (sid, t)
-    # streams 0, 1 and the half-pel one against the oracle directly
-    for sid in (0, 1, len(streams) - 1):
+    # streams 0, 1, the half-pel one and the p = 64 ones against the oracle directly
+    for sid in (0, 1, 4, 5, 6):
         frames, blk, p, lam, algo = streams[sid]
         prm, a = _prm(blk, lam, algo)
         oprm = oracle.Params(lam=prm.lam, qp=prm.qp, alpha=prm.alpha, beta=prm.beta,
@@ -80,6 +93,10 @@ def test_served_results_equal_alone_in_a_mix():
     assert st["completed"] == total
     assert 0 < st["p50_us"] <= st["p99_us"]
     assert st["throughput_rps"] > 0
+    say(f"lanes {lanes}: {st['passes']} passes, {st['mean_batch']:.2f} requests a pass, "
+        f"device busy {st['device_busy_frac']:.2f}")
+    assert st["passes"] < total and st["mean_batch"] > 1  # requests were gathered
+    assert 0 < st["device_busy_frac"] <= 1
 
 
 def test_serve_rejects_what_can_never_fit_and_bad_requests():
