@@ -197,6 +197,25 @@ int acbm_acbm_frame(const acbm_geom* g, const acbm_params* prm, const uint8_t* c
                     const uint8_t* ref, const acbm_mv* prev_field, acbm_block_result* out,
                     void* ws, size_t ws_bytes, void* stream);
 
+/* ACBM for one frame pair that allocates nothing, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * hosts that forbid hipMalloc).  Same arguments and results as
+ * acbm_acbm_frame, without a workspace: the scratch (a dependency-wait
+ * header, the row order, the published vector words and the job tables) is
+ * a fixed 2 MiB device array inside the library, one per GPU, held until the
+ * process ends; frames of more than about 520,000 blocks need more and are
+ * rejected with ACBM_E_NOMEM before anything is enqueued.  Every call on a
+ * GPU shares that GPU's array, so calls that overlap on one GPU (other
+ * streams, other host threads) race and must be serialised by the caller.
+ * No hipMalloc, hipFree or allocating library call is made (acbm_init looks
+ * the array up ahead of time; otherwise the first call on a device does).
+ * status (device memory, may be NULL) receives 0 when every block finished,
+ * or 1 when a dependency wait gave up (the results are then incomplete), in
+ * stream order after the results. */
+int acbm_acbm_frame_noalloc(const acbm_geom* g, const acbm_params* prm, const uint8_t* cur,
+                            const uint8_t* ref, const acbm_mv* prev_field,
+                            acbm_block_result* out, uint32_t* status, void* stream);
+
 /* ---- batches of sequences ----------------------------------------------- */
 /* A job is one sequence: frame t-1 is the reference of frame t, so nframes
  * frames give nframes-1 pairs; PBM/ACBM take pair t-1's field as pair t's

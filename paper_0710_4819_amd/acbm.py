@@ -134,6 +134,7 @@ def lib():
         L.acbm_fsbm_frame.argtypes = [P(Geom), P(CParams), vp, vp, vp, vp, sz, vp]
         L.acbm_pbm_frame.argtypes = [P(Geom), P(CParams), vp, vp, vp, vp, vp, sz, vp]
         L.acbm_acbm_frame.argtypes = [P(Geom), P(CParams), vp, vp, vp, vp, vp, sz, vp]
+        L.acbm_acbm_frame_noalloc.argtypes = [P(Geom), P(CParams), vp, vp, vp, vp, vp, vp]
         L.acbm_batch_workspace_size.argtypes = [P(Job), sz, P(sz)]
         L.acbm_batch.argtypes = [P(Job), sz, vp, sz, vp]
         L.acbm_batch_status.argtypes = [P(Job), sz, vp, sz, vp, P(C.c_int)]
@@ -268,6 +269,25 @@ def acbm_frame(cur, ref, block_w, block_h, p, params: Params, prev_field=None, w
                ws=None, stream=None) -> torch.Tensor:
     return _predictive(lib().acbm_acbm_frame, OP_ACBM, cur, ref, block_w, block_h, p, params,
                        prev_field, width, ws, stream)
+
+
+def acbm_frame_noalloc(cur, ref, block_w, block_h, p, params: Params, prev_field=None,
+                       width=None, status: torch.Tensor | None = None,
+                       stream=None) -> torch.Tensor:
+    """ACBM for one pair through acbm_acbm_frame_noalloc (the library's own
+    fixed scratch, no workspace).  status: optional int32 device tensor of
+    one element that receives the run status (0 = every block finished)."""
+    g = geom(cur, block_w, block_h, p, width)
+    out = _results(g, cur.device)
+    if prev_field is not None:
+        by, bx = _blocks(g)
+        if prev_field.dtype != torch.int16 or tuple(prev_field.shape) != (by, bx, 2):
+            raise ValueError("prev_field must be an int16 [by, bx, 2] tensor")
+        prev_field = prev_field.contiguous()
+    _check(lib().acbm_acbm_frame_noalloc(C.byref(g), C.byref(params.c()), cur.data_ptr(),
+                                         ref.data_ptr(), _ptr(prev_field), out.data_ptr(),
+                                         _ptr(status), _stream(stream)))
+    return out
 
 
 class Batch:

@@ -330,8 +330,9 @@ int acbm_default_params(uint32_t block_w, uint32_t block_h, uint32_t lambda, uin
 
 int acbm_init(void) {
   t_last_error.clear();
-  const int rc = check_device();
-  return rc ? rc : batch_side_streams_init();
+  int rc = check_device();
+  if (!rc) rc = batch_side_streams_init();
+  return rc ? rc : noalloc_scratch_init();
 }
 
 int acbm_workspace_size(int op, const acbm_geom* g, uint32_t npairs, size_t* bytes) {

@@ -162,6 +162,9 @@ int launch_search_batch(int N, int M, const SearchPlan& pl, size_t lds, const Ba
                         int njobs, uint32_t items, hipStream_t s);
 // Creates the current device's side streams for batch walker launches.
 int batch_side_streams_init();
+// Looks up the current device's scratch array of the allocation-free entry
+// point (once per device).
+int noalloc_scratch_init();
 // acbm_batch with a temporal field for the first pair of each PBM/ACBM job
 // (prev0[i], may be null; prev0 itself may be null) and the choice of side
 // streams; status_words (may be null) receives the device addresses of the
