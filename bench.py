@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the served-requests leg")
     ap.add_argument("--serve-seconds", type=float, default=1.5,
                     help="duration of each arrival rate of the served leg")
+    ap.add_argument("--serve-lanes", type=int, default=4,
+                    help="passes the server keeps in flight (HIP streams)")
     ap.add_argument("--walker-phases", action="store_true",
                     help="report the row walkers' per-phase times (needs the profiling build: "
                          "ACBM_LIB=paper_0710_4819_amd/libacbm_phases.so, built by "
@@ -361,7 +363,7 @@ def latency_leg(torch, acbm, frames, prm, stream, reps=5):
 
 
 def served_leg(torch, acbm, synth, rates, seconds, algo_names=("fsbm", "acbm"), nstreams=32,
-               nfr=3, sat_requests=3000):
+               nfr=3, sat_requests=3000, lanes=4):
     """Poisson arrivals of frame-pair requests over 32 streams whose
     resolution (640x480 .. 3840x2160) and p (16, 32, 64) are drawn per stream;
     each stream cycles over nfr generated frames.  The server gathers the
@@ -376,7 +378,7 @@ def served_leg(torch, acbm, synth, rates, seconds, algo_names=("fsbm", "acbm"), 
     frames = [synth.stream_frames(sp, nfr) for sp in specs]
     prm = acbm.default_params(16, 16, 8)
     out = {"workload": f"{nstreams} streams, 640x480..3840x2160, p 16/32/64, 16x16 blocks, "
-                       "lambda 8, Poisson arrivals", "lanes": 4, "max_inflight": 64}
+                       "lambda 8, Poisson arrivals", "lanes": lanes, "max_inflight": 64}
     algos = {"fsbm": acbm.ALGO_FSBM, "acbm": acbm.ALGO_ACBM, "pbm": acbm.ALGO_PBM}
 
     def one_rate(algo, rate, n, nthreads=4):
@@ -387,7 +389,7 @@ def served_leg(torch, acbm, synth, rates, seconds, algo_names=("fsbm", "acbm"), 
         import threading
         times, sids = synth.serve_arrivals(rate if rate else 1e9, n, nstreams)
         srv = acbm.Server(pool_bytes=24 << 30, max_streams=nstreams, max_inflight=64,
-                          queue_depth=16384, lanes=4, pinned_bytes=2 << 30)
+                          queue_depth=16384, lanes=lanes, pinned_bytes=2 << 30)
         try:
             first = [srv.submit(s, frames[s][0], 16, 16, specs[s]["p"], prm, algo)
                      for s in range(nstreams)]
@@ -638,7 +640,8 @@ def main():
         out["batched"] = batched_leg(torch, acbm, synth, dev)
         log("batched leg done")
     if args.only in (None, "serve") and not args.no_serve:
-        out["served"] = served_leg(torch, acbm, synth, [200, 500, 1000, 2000], args.serve_seconds)
+        out["served"] = served_leg(torch, acbm, synth, [200, 500, 1000, 2000], args.serve_seconds,
+                                   lanes=args.serve_lanes)
     if do_f and "roofline" in out:
         ev = probe_peak()
         if ev:

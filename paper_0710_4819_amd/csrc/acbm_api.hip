@@ -264,6 +264,7 @@ void save_tuned_plan(int N, int M, int p, const SearchPlan& pl, float ms) {
 
 SearchPlan plan_search(int N, int M, int p, int max_threads) {
   const char* force = std::getenv("ACBM_R");
+  if (force && !*force) force = nullptr;  // set but empty: as if unset
   if (!force && max_threads >= 1024) {
     std::lock_guard<std::mutex> lk(g_tuned_mu);
     load_tune_cache_locked();

@@ -953,6 +953,7 @@ static int row_threads(int njobs) {
 static int pick_rows(const KGeom& g, int nt, size_t total_rows, bool hp) {
   const bool shared_cus = total_rows > (size_t)device_cus();
   const char* force = std::getenv("ACBM_PRED_R");
+  if (force && !*force) force = nullptr;  // set but empty: as if unset
   if (!force && shared_cus) {
     for (int R = (g.bw == 16 && !hp) ? 3 : 1; R >= 1; --R)
       if (ring_bytes(ring_for(g, R)) <= (size_t)lds_limit()) return R;
