@@ -175,17 +175,29 @@ static SearchPlan plan_for(int N, int M, int p, int R, int max_threads, double* 
   return SearchPlan{R, threads, lds};
 }
 
-SearchPlan plan_search_model(int N, int M, int p, int R) {
+// A 2x2 tile of 8x8 blocks is searched over the tile's 16x16 window with the
+// 16x16 search's QSAD count; its four blocks keep four sets of R
+// accumulators, so R stays at 6 or below (104 VGPRs at R = 6; R = 8 spills
+// under the 1024-thread register budget of 128).
+static bool tile_rows_ok(int R) { return R <= 6; }
+
+SearchPlan plan_search_model(int N, int M, int p, int R, int tile) {
   double cost = 0;
+  if (tile == 2) {
+    if (N != 8 || M != 8 || !tile_rows_ok(R)) return SearchPlan{0, 0, 0};
+    SearchPlan pl = plan_for(16, 16, p, R, 1024, &cost);
+    pl.tile = 2;
+    return pl;
+  }
   return plan_for(N, M, p, R, 1024, &cost);
 }
 
 namespace {
 std::mutex g_tuned_mu;
-std::map<std::tuple<int, int, int>, SearchPlan> g_tuned;
+std::map<std::tuple<int, int, int, int>, SearchPlan> g_tuned;  // (N, M, p, tile)
 // Plans read from the tuning cache, with the time per pair they were
 // measured at (acbm_autotune returns these without timing again).
-std::map<std::tuple<int, int, int>, float> g_cached_ms;
+std::map<std::tuple<int, int, int, int>, float> g_cached_ms;
 bool g_cache_loaded = false;
 
 // Architecture name of the current device without its feature suffix
@@ -201,7 +213,8 @@ std::string device_arch() {
 
 // The tuning cache named by ACBM_TUNE_CACHE: one JSON object per line,
 // {"arch": "gfx950", "N": 16, "M": 16, "p": 32, "R": 6, "ms_per_pair": 0.0887},
-// appended by acbm_autotune; a later line for the same key wins.  Lines of
+// with "tile": 2 at the end for a plan of 2x2 tiles of 8x8 blocks, appended
+// by acbm_autotune; a later line for the same key wins.  Lines of
 // another architecture or with a plan that no longer fits are ignored.
 // g_tuned_mu is held.
 void load_tune_cache_locked() {
@@ -223,10 +236,11 @@ void load_tune_cache_locked() {
         arch != a)
       continue;
     if ((N != 8 && N != 16) || (M != 8 && M != 16) || p < 0 || p > 127) continue;
-    const SearchPlan pl = plan_search_model(N, M, p, R);
+    const int tile = std::strstr(line, "\"tile\": 2") ? 2 : 1;
+    const SearchPlan pl = plan_search_model(N, M, p, R, tile);
     if (!pl.R) continue;
-    g_tuned[std::make_tuple(N, M, p)] = pl;
-    g_cached_ms[std::make_tuple(N, M, p)] = ms;
+    g_tuned[std::make_tuple(N, M, p, tile)] = pl;
+    g_cached_ms[std::make_tuple(N, M, p, tile)] = ms;
   }
   std::fclose(f);
 }
@@ -234,13 +248,13 @@ void load_tune_cache_locked() {
 
 void set_tuned_plan(int N, int M, int p, const SearchPlan& pl) {
   std::lock_guard<std::mutex> lk(g_tuned_mu);
-  g_tuned[std::make_tuple(N, M, p)] = pl;
+  g_tuned[std::make_tuple(N, M, p, pl.tile)] = pl;
 }
 
-bool cached_plan(int N, int M, int p, SearchPlan* pl, float* ms) {
+bool cached_plan(int N, int M, int p, int tile, SearchPlan* pl, float* ms) {
   std::lock_guard<std::mutex> lk(g_tuned_mu);
   load_tune_cache_locked();
-  auto it = g_cached_ms.find(std::make_tuple(N, M, p));
+  auto it = g_cached_ms.find(std::make_tuple(N, M, p, tile));
   if (it == g_cached_ms.end()) return false;
   *pl = g_tuned[it->first];
   *ms = it->second;
@@ -250,16 +264,69 @@ bool cached_plan(int N, int M, int p, SearchPlan* pl, float* ms) {
 void save_tuned_plan(int N, int M, int p, const SearchPlan& pl, float ms) {
   std::lock_guard<std::mutex> lk(g_tuned_mu);
   load_tune_cache_locked();
-  g_tuned[std::make_tuple(N, M, p)] = pl;
+  const auto key = std::make_tuple(N, M, p, pl.tile);
+  g_tuned[key] = pl;
   const char* path = std::getenv("ACBM_TUNE_CACHE");
   if (!path || !*path) return;
-  g_cached_ms[std::make_tuple(N, M, p)] = ms;
+  g_cached_ms[key] = ms;
   FILE* f = std::fopen(path, "a");
   if (!f) return;  // an unwritable cache only costs the next process a re-tune
   std::fprintf(f, "{\"arch\": \"%s\", \"N\": %d, \"M\": %d, \"p\": %d, \"R\": %d, "
-                  "\"ms_per_pair\": %.6f}\n",
-               device_arch().c_str(), N, M, p, pl.R, ms);
+                  "\"ms_per_pair\": %.6f%s}\n",
+               device_arch().c_str(), N, M, p, pl.R, ms, pl.tile == 2 ? ", \"tile\": 2" : "");
   std::fclose(f);
+}
+
+bool tiles_apply(const KGeom& g) {
+  static const bool off = [] {
+    const char* e = std::getenv("ACBM_SEARCH_TILES");
+    return e && *e && std::atoi(e) == 0;
+  }();
+  return !off && g.bw == 8 && g.bh == 8 && g.bx % 2 == 0 && g.by % 2 == 0 && g.nb >= 4;
+}
+
+// The tiled plan: a measured one if there is, else the cost model's choice
+// among the row blockings a tile can keep in registers (ACBM_R overrides).
+static SearchPlan plan_search_tile(int p) {
+  const char* force = std::getenv("ACBM_R");
+  if (force && !*force) force = nullptr;
+  if (!force) {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    load_tune_cache_locked();
+    auto it = g_tuned.find(std::make_tuple(8, 8, p, 2));
+    if (it != g_tuned.end()) return it->second;
+  }
+  SearchPlan best{0, 0, 0};
+  double best_cost = 1e300;
+  for (int R : kPlanRs) {
+    if (!tile_rows_ok(R) || (force && std::atoi(force) != R)) continue;
+    double cost = 0;
+    SearchPlan pl = plan_for(16, 16, p, R, 1024, &cost);
+    if (pl.R && cost < best_cost) {
+      best_cost = cost;
+      best = pl;
+      best.tile = 2;
+    }
+  }
+  return best;
+}
+
+SearchPlan plan_fsbm_search(const KGeom& g) {
+  if (tiles_apply(g)) {
+    const SearchPlan t = plan_search_tile(g.p);
+    if (t.R) return t;
+  }
+  return plan_search(g.bw, g.bh, g.p);
+}
+
+// Row blockings measured on MI355X where the cost model's choice is not the
+// fastest: 16x16, p = 64: R = 6 1.38 ms per 3840x2160 pair against 1.74 for
+// the model's R = 8 (0.37 against 0.45 ms at 1920x1088), though both run 7
+// waves per SIMD.  A plan tuned in this process or read from the tuning
+// cache still comes first.
+static int measured_rows(int N, int M, int p) {
+  if (N == 16 && M == 16 && p == 64) return 6;
+  return 0;
 }
 
 SearchPlan plan_search(int N, int M, int p, int max_threads) {
@@ -268,8 +335,13 @@ SearchPlan plan_search(int N, int M, int p, int max_threads) {
   if (!force && max_threads >= 1024) {
     std::lock_guard<std::mutex> lk(g_tuned_mu);
     load_tune_cache_locked();
-    auto it = g_tuned.find(std::make_tuple(N, M, p));
+    auto it = g_tuned.find(std::make_tuple(N, M, p, 1));
     if (it != g_tuned.end()) return it->second;
+  }
+  if (!force && max_threads >= 1024 && measured_rows(N, M, p)) {
+    double cost = 0;
+    const SearchPlan pl = plan_for(N, M, p, measured_rows(N, M, p), max_threads, &cost);
+    if (pl.R) return pl;
   }
   SearchPlan best{0, 0, 0};
   double best_cost = 1e300;

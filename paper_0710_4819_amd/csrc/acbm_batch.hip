@@ -2,7 +2,8 @@
 //
 // FSBM jobs (Section 2.3) are grouped by block size and window-search plan
 // (at most 64 jobs a group); each group runs as one full-search launch with
-// a workgroup per (job, pair, block) item, then a single resolve launch
+// a workgroup per (job, pair, block) item (per 2x2 tile of 8x8 blocks with a
+// tiled plan), then a single resolve launch
 // takes every pair of every FSBM job at once.  PBM/ACBM jobs (Sections 2.2,
 // 3.2) are grouped by block size and precision (at most 256 jobs a group);
 // each group runs as one row-walker launch whose walkers take the rows of
@@ -71,6 +72,9 @@ struct Class {
   std::vector<size_t> job_index;  // into the caller's job array
   uint32_t items = 0;
   size_t lds_search = 0;
+  size_t lds_resolve = 0;  // the resolve of this class's pairs
+  uint32_t pair0 = 0, pairs = 0;
+  int steps = 0;           // longest anti-diagonal walk of its resolves, bx + 2(by - 1)
 };
 
 struct Plan {
@@ -92,7 +96,7 @@ struct Plan {
 // job table, its frame pointers], then the scratch region [per walker group:
 // header, row order].
 int make_plan(const acbm_job* jobs, size_t njobs, Plan* pl) {
-  std::map<std::tuple<int, int, int, int>, size_t> cls;
+  std::map<std::tuple<int, int, int, int, int>, size_t> cls;
   std::map<std::tuple<int, int, int>, size_t> pcls;
   size_t off = 0;
   pl->slice.resize(njobs);
@@ -134,9 +138,9 @@ int make_plan(const acbm_job* jobs, size_t njobs, Plan* pl) {
     }
     KGeom k;
     check_geom(&j.geom, &k);
-    const SearchPlan sp = plan_search(k.bw, k.bh, k.p);
+    const SearchPlan sp = plan_fsbm_search(k);
     if (!sp.R) return fail(ACBM_E_UNSUPPORTED, "search window does not fit in LDS");
-    const auto key = std::make_tuple(k.bw, k.bh, sp.R, sp.threads);
+    const auto key = std::make_tuple(k.bw, k.bh, sp.R, sp.threads, sp.tile);
     auto it = cls.find(key);
     if (it != cls.end() && pl->classes[it->second].jobs.size() == 64) {
       cls.erase(it);  // a full group: later jobs of this kind open a new one
@@ -151,30 +155,41 @@ int make_plan(const acbm_job* jobs, size_t njobs, Plan* pl) {
     }
     Class& c = pl->classes[it->second];
     const uint32_t npairs = j.nframes - 1;
-    if ((uint64_t)c.items + (uint64_t)npairs * k.nb > 0xFFFFFFFFull)
+    const uint32_t per_pair = sp.tile == 2 ? (uint32_t)k.nb / 4 : (uint32_t)k.nb;  // items
+    if ((uint64_t)c.items + (uint64_t)npairs * per_pair > 0xFFFFFFFFull)
       return fail(ACBM_E_RANGE, "too many blocks in one batch group");
     BatchJob bj{};
     bj.g = k;
-    bj.s = window_shape_host(k.bw, k.bh, k.p, sp.R);
+    bj.s = sp.tile == 2 ? window_shape_host(16, 16, k.p, sp.R)
+                        : window_shape_host(k.bw, k.bh, k.p, sp.R);
     bj.slack = fsbm_slack(k.p, j.params);
     bj.lam = j.params.lambda;
     bj.subpel = j.params.subpel;
     bj.npairs = npairs;
     bj.item0 = c.items;
-    c.items += npairs * (uint32_t)k.nb;
+    c.items += npairs * per_pair;
     c.lds_search = std::max<size_t>(c.lds_search, (size_t)sp.lds_bytes);
-    if (fsbm_mv_in_lds(k)) pl->lds_resolve = std::max<size_t>(pl->lds_resolve, (size_t)k.nb * 4);
+    if (fsbm_mv_in_lds(k)) c.lds_resolve = std::max<size_t>(c.lds_resolve, (size_t)k.nb * 4);
+    c.steps = std::max(c.steps, k.bx + 2 * (k.by - 1));
     c.jobs.push_back(bj);
     c.job_index.push_back(i);
     pl->njob_fsbm += 1;
     pl->nptr += j.nframes;
   }
+  // Classes whose resolves walk the most anti-diagonal steps search first,
+  // so that with a side stream their resolves overlap the later searches.
+  std::stable_sort(pl->classes.begin(), pl->classes.end(),
+                   [](const Class& a, const Class& b) { return a.steps > b.steps; });
   // resolve workgroups are numbered across all FSBM jobs, in table order
-  for (Class& c : pl->classes)
+  for (Class& c : pl->classes) {
+    c.pair0 = pl->pairs;
     for (BatchJob& bj : c.jobs) {
       bj.pair0 = pl->pairs;
       pl->pairs += bj.npairs;
     }
+    c.pairs = pl->pairs - c.pair0;
+    pl->lds_resolve = std::max(pl->lds_resolve, c.lds_resolve);
+  }
   pl->jobs_bytes = off;
   pl->table_off = off;
   pl->off_jobs = 0;
@@ -321,6 +336,7 @@ struct SidePool {
   hipStream_t s[kSideStreams] = {};
   hipEvent_t fork = nullptr;
   hipEvent_t join[kSideStreams] = {};
+  hipEvent_t searched = nullptr;  // a search class done: its resolve may start
 };
 std::mutex g_side_mu;
 std::map<int, SidePool> g_side;
@@ -339,6 +355,7 @@ int side_pool(int dev, SidePool** out) {
   if (it == g_side.end()) {
     SidePool p;
     hipError_t e = hipEventCreateWithFlags(&p.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p.searched, hipEventDisableTiming);
     for (int i = 0; i < kSideStreams && e == hipSuccess; ++i) {
       e = hipStreamCreateWithFlags(&p.s[i], hipStreamNonBlocking);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&p.join[i], hipEventDisableTiming);
@@ -349,6 +366,7 @@ int side_pool(int dev, SidePool** out) {
         if (p.join[i]) (void)hipEventDestroy(p.join[i]);
       }
       if (p.fork) (void)hipEventDestroy(p.fork);
+      if (p.searched) (void)hipEventDestroy(p.searched);
       return hip_fail(e, "creating the batch's side streams");
     }
     it = g_side.emplace(dev, p).first;
@@ -358,7 +376,7 @@ int side_pool(int dev, SidePool** out) {
 }
 
 int enqueue_fsbm(const acbm_job* jobs, const Plan& pl, char* base, const BatchJob* all,
-                 hipStream_t st);
+                 hipStream_t st, hipStream_t rs, hipEvent_t searched);
 
 }  // namespace
 
@@ -404,15 +422,19 @@ int enqueue_batch(const acbm_job* jobs, size_t njobs, const acbm_mv* const* prev
   // Walker launches: the groups, then the jobs that run alone, round robin
   // over the side streams and, when the batch has no FSBM job, `st` as well.
   // (Two side streams can share a hardware queue and then run one after the
-  // other; `st` and a side stream were measured to run side by side.)
+  // other; `st` and a side stream were measured to run side by side.)  With
+  // several FSBM search classes, one more side stream takes their resolves,
+  // each starting when its class's search is done, beside the later searches.
   const size_t nunits = pl.pgroups.size() + pl.predictive.size();
   const bool has_fsbm = !pl.classes.empty();
   const size_t off_st = has_fsbm ? nunits : nunits - std::min<size_t>(nunits, 1);
+  const bool resolve_side = pl.classes.size() > 1;
   std::unique_lock<std::mutex> lk(g_side_mu, std::defer_lock);
   SidePool* sp = nullptr;
   int nside = 0;
-  int want = allow_side ? std::min<int>(side_streams(), (int)std::min<size_t>(kSideStreams, off_st))
-                        : 0;
+  const int want_w =
+      allow_side ? std::min<int>(side_streams(), (int)std::min<size_t>(kSideStreams, off_st)) : 0;
+  int want = allow_side ? std::min<int>(side_streams(), want_w + (resolve_side ? 1 : 0)) : 0;
   if (want > 0) {
     int cur = -1;
     hipDevice_t sdev = -1;
@@ -455,10 +477,14 @@ int enqueue_batch(const acbm_job* jobs, size_t njobs, const acbm_mv* const* prev
         break;
       }
   }
-  const int lanes = nside + (has_fsbm && nside ? 0 : 1);  // lane nside is `st`
+  const int nside_w = std::min(nside, want_w);  // side streams of walker launches
+  // the resolve stream: a side stream of its own when one is left, else the
+  // last walker stream
+  hipStream_t rs = resolve_side && nside > 0 ? sp->s[nside - 1] : nullptr;
+  const int lanes = nside_w + (has_fsbm && nside_w ? 0 : 1);  // lane nside_w is `st`
   for (size_t u = 0; u < nunits && !rc; ++u) {
     const int lane = (int)(u % lanes);
-    hipStream_t su = lane < nside ? sp->s[lane] : st;
+    hipStream_t su = lane < nside_w ? sp->s[lane] : st;
     if (u < pl.pgroups.size()) {
       const PGroup& pg = pl.pgroups[u];
       rc = launch_predictive_group(
@@ -478,7 +504,7 @@ int enqueue_batch(const acbm_job* jobs, size_t njobs, const acbm_mv* const* prev
                              prev0 ? prev0[i] : nullptr, base + pl.slice[i], b, j.out, su);
     }
   }
-  if (!rc) rc = enqueue_fsbm(jobs, pl, base, all, st);
+  if (!rc) rc = enqueue_fsbm(jobs, pl, base, all, st, rs, rs ? sp->searched : nullptr);
   // join every forked stream, after an error too, so that a capture of `st`
   // still ends with every branch joined
   for (int i = 0; i < nside; ++i) {
@@ -490,11 +516,15 @@ int enqueue_batch(const acbm_job* jobs, size_t njobs, const acbm_mv* const* prev
 }
 
 // The FSBM jobs of a batch on `st`: a search launch per group, the half-pel
-// preparation of half-pel jobs, and one resolve over every FSBM pair.
+// preparation of half-pel jobs, and one resolve over every FSBM pair; or,
+// with a resolve stream `rs` (forked from `st` and joined back by the
+// caller), resolve launches on `rs` that start as soon as their groups are
+// searched.
 int enqueue_fsbm(const acbm_job* jobs, const Plan& pl, char* base, const BatchJob* all,
-                 hipStream_t st) {
+                 hipStream_t st, hipStream_t rs, hipEvent_t searched) {
   int rc = ACBM_OK;
   size_t jo = 0;
+  size_t pend = 0, pend_jo = 0;  // first class (and its job) not yet resolved
   for (const Class& c : pl.classes) {
     const acbm_job& j0 = jobs[c.job_index[0]];
     if (c.jobs.size() == 1 && j0.nframes - 1 <= (uint32_t)kMaxPairsPerLaunch) {
@@ -531,9 +561,28 @@ int enqueue_fsbm(const acbm_job* jobs, const Plan& pl, char* base, const BatchJo
       }
     }
     jo += c.jobs.size();
+    // With a resolve stream, the classes whose resolves walk the same longest
+    // chain resolve in one launch once the last of them is searched (one
+    // launch, so their pairs resolve side by side rather than one class
+    // after the other on the stream); the classes sort by that chain, so
+    // the long resolves overlap the searches of the classes after them.
+    const size_t ci = (size_t)(&c - pl.classes.data());
+    if (rs && (ci + 1 == pl.classes.size() || pl.classes[ci + 1].steps < c.steps)) {
+      hipError_t e = hipEventRecord(searched, st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(rs, searched, 0);
+      if (e != hipSuccess) return hip_fail(e, "ordering a batch resolve after its search");
+      const Class& c0 = pl.classes[pend];
+      size_t lds = 0;
+      for (size_t k = pend; k <= ci; ++k) lds = std::max(lds, pl.classes[k].lds_resolve);
+      if ((rc = launch_resolve_batch(all + pend_jo, (int)(jo - pend_jo), c0.pair0,
+                                     c.pair0 + c.pairs - c0.pair0, lds, rs)))
+        return rc;
+      pend = ci + 1;
+      pend_jo = jo;
+    }
   }
-  if (pl.njob_fsbm &&
-      (rc = launch_resolve_batch(all, (int)pl.njob_fsbm, pl.pairs, pl.lds_resolve, st)))
+  if (!rs && pl.njob_fsbm &&
+      (rc = launch_resolve_batch(all, (int)pl.njob_fsbm, 0, pl.pairs, pl.lds_resolve, st)))
     return rc;
   return ACBM_OK;
 }

@@ -292,6 +292,39 @@ __device__ __forceinline__ void task_sads(const uint32_t* __restrict__ win, int 
   }
 }
 
+// The same task over a 16x16 tile of four 8x8 blocks: acc[b][rr] holds the
+// SADs of block b (b = 2 * (row >= 8) + (column >= 8) within the tile).  A
+// block's SAD at a displacement is one quadrant of the tile's, so the four
+// blocks cost the QSADs of one 16x16 task.
+template <int R>
+__device__ __forceinline__ void task_sads_tile(const uint32_t* __restrict__ win, int stride,
+                                               int q, int g, const CurBlock<16, 16>& cb,
+                                               uint64_t (&acc)[4][R]) {
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) acc[b][rr] = 0;
+  const uint32_t* base = win + (R * g) * stride + q;
+#pragma unroll
+  for (int w = 0; w < R + 15; ++w) {
+    const uint32_t* rowp = base + w * stride;
+    uint64_t qw[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qw[k] = (uint64_t)rowp[k] | ((uint64_t)rowp[k + 1] << 32);
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      const int j = w - rr;
+      if (j >= 0 && j < 16) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int b = 2 * (j >> 3) + (k >> 1);
+          acc[b][rr] = __builtin_amdgcn_qsad_pk_u16_u8(qw[k], cb.d[j][k], acc[b][rr]);
+        }
+      }
+    }
+  }
+}
+
 // Validity of candidate (u, v) for the block at (x0, y0) (frame border and
 // |u|, |v| <= p).
 __device__ __forceinline__ bool cand_valid(int u, int v, int p, int x0, int y0, int N, int M,

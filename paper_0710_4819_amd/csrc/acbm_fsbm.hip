@@ -9,6 +9,8 @@
 //            with V_QSAD_PK_U16_U8.  Output: either the whole table
 //            (acbm_sad_table) or, for FSBM, the block's SAD minimum and the
 //            few candidates that can still win once the rate term is added.
+//            8x8 blocks on an even grid search in 2x2 tiles instead
+//            (k_search_tile: one workgroup, four blocks, the 16x16 window).
 //  k_resolve one workgroup per frame pair.  The predictor of a block depends
 //            on the final vectors of its left, top and top-right neighbours,
 //            so the argmin of J is sequential in raster order; the kernel
@@ -308,6 +310,176 @@ k_search_batch(const BatchJob* __restrict__ jobs, int njobs, uint32_t items) {
   search_block<N, M, R, kKindFsbm>(g, J.s, J.frames[pair], J.frames[pair + 1], b, nullptr,
                                J.recs + at, J.ovf + at * ovf_stride(g.p), J.slack, win, red,
                                &n_keep);
+}
+
+// ---------------------------------------------------------------------------
+// Window search of a 2x2 tile of 8x8 blocks by one workgroup (FSBM records
+// only).  The tile's 16x16 window holds every candidate of its four blocks;
+// one pass of 16x16 tasks gives each block its SADs (task_sads_tile), and the
+// epilogue of search_block runs once per block: border masks from the
+// block's own position, SAD minimum, possible winners, record and overflow
+// region.  Against four workgroups of one block each, the tile loads one
+// 80x80 window instead of four 72x72 ones (p = 32), reads fewer LDS dwords
+// per QSAD and pays the per-workgroup costs once.  `t` is the tile index in
+// the frame's grid of (bx/2) x (by/2) tiles; `recs` and `ovf` are the pair's.
+// ---------------------------------------------------------------------------
+template <int R>
+__device__ __forceinline__ void search_tile(const KGeom& g, const WindowShape& s,
+                                            const uint8_t* __restrict__ ref,
+                                            const uint8_t* __restrict__ cur, int t,
+                                            BlockRec* __restrict__ recs,
+                                            uint16_t* __restrict__ ovf, uint32_t slack,
+                                            uint32_t* win, uint32_t* red, uint32_t* n_keep) {
+  const int tbx = g.bx >> 1;
+  const int tr = t / tbx, tc = t - tr * tbx;
+  const int x0 = tc * 16, y0 = tr * 16;
+  const int p = s.p, W = 2 * p + 1;
+
+  load_window<16, 16>(win, s, ref, g.pitch, g.width, g.height, x0, y0);
+  CurBlock<16, 16> cb;
+  load_cur_uniform<16, 16>(cb, cur, g.pitch, x0, y0);
+  uint32_t intra[4] = {0, 0, 0, 0};
+  if (threadIdx.x < 64) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      intra[b] = wave_intra_x<8, 8>(cur, g.pitch, x0 + 8 * (b & 1), y0 + 8 * (b >> 1));
+  }
+  if (threadIdx.x < 4) n_keep[threadIdx.x] = 0;
+  __syncthreads();
+
+  const int tasks = s.quads * s.groups;
+  const int th = threadIdx.x;
+  const bool active = th < tasks;
+  const int gi = active ? (int)__umulhi((uint32_t)th, s.qmagic) : 0;  // th / quads
+  const int q = active ? th - gi * s.quads : 0;
+  uint64_t acc[4][R];
+  if (active) task_sads_tile<R>(win, s.stride, q, gi, cb, acc);
+
+  const int u0 = s.u_lo + 4 * q, v0 = -p + R * gi;
+  uint32_t lmin[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const ValidBox vbox =
+        valid_box(p, x0 + 8 * (b & 1), y0 + 8 * (b >> 1), 8, 8, g.width, g.height);
+    const bool whole = vbox.u_min == -p && vbox.u_max == p && vbox.v_min == -p && vbox.v_max == p;
+    if (active) {
+      if (whole)
+        mask_padding<R>(acc[b], p, u0, v0);
+      else
+        mask_invalid<R>(acc[b], vbox, u0, v0);
+    }
+    lmin[b] = active ? min_u16_lanes<R>(acc[b]) : 0xFFFFu;
+  }
+  // the four blocks' minima over the workgroup: one slot per (wave, block)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const uint32_t m = wave_min_u32(lmin[b]);
+    if (lane == 0) red[4 * wave + b] = m;
+  }
+  __syncthreads();
+  uint32_t smin[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    uint32_t m = red[b];
+    for (int w = 1; w < nw; ++w) m = min(m, red[4 * w + b]);
+    smin[b] = m;
+  }
+
+  const uint32_t cap = ovf_list_cap(p);
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const uint32_t thr = (uint32_t)min<uint64_t>((uint64_t)smin[b] + slack, 0xFFFEu);
+    if (active && lmin[b] <= thr) {  // rare: this lane holds a possible winner of block b
+      const int blk = (2 * tr + (b >> 1)) * g.bx + 2 * tc + (b & 1);
+      BlockRec* __restrict__ rec = recs + blk;
+      uint32_t* __restrict__ list = reinterpret_cast<uint32_t*>(ovf + (size_t)blk * ovf_stride(p));
+      uint32_t mine = 0;
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) mine += ((uint32_t)(acc[b][rr] >> (16 * i)) & 0xFFFFu) <= thr;
+      uint32_t slot = atomicAdd(&n_keep[b], mine);
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t sad = (uint32_t)(acc[b][rr] >> (16 * i)) & 0xFFFFu;
+          if (sad <= thr) {
+            const uint32_t e = (sad << 16) | (uint32_t)((v0 + rr + p) * W + (u0 + i + p));
+            if (slot < (uint32_t)kShort) rec->e[slot] = e;
+            if (slot < cap) list[slot] = e;  // used when kShort < total <= cap
+            ++slot;
+          }
+        }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const uint32_t total = n_keep[b];
+    const int blk = (2 * tr + (b >> 1)) * g.bx + 2 * tc + (b & 1);
+    uint16_t* __restrict__ row = ovf + (size_t)blk * ovf_stride(p);
+    // more candidates than the list holds: the whole row of SADs instead
+    // (written after the barrier, so it replaces any list entries)
+    if (total > cap && active) {
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) {
+        const int v = v0 + rr;
+        if (v > p) break;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int u = u0 + i;
+          if (u < -p || u > p) continue;
+          row[(v + p) * W + (u + p)] = (uint16_t)(acc[b][rr] >> (16 * i));
+        }
+      }
+    }
+    if (threadIdx.x == 0) {
+      BlockRec* __restrict__ rec = recs + blk;
+      rec->sad_min = smin[b];
+      rec->count = total;
+      rec->intra_x = intra[b];
+    }
+  }
+}
+
+// One workgroup per (2x2 tile, pair).
+template <int R>
+__global__ void __launch_bounds__(1024)
+k_search_tile(const KGeom g, const WindowShape s, const FramePtrs fr, BlockRec* __restrict__ recs,
+              uint16_t* __restrict__ ovf, uint32_t slack) {
+  extern __shared__ uint32_t win[];
+  __shared__ uint32_t red[64];
+  __shared__ uint32_t n_keep[4];
+  const int nt = g.nb >> 2;
+  const int t = xcd_band(blockIdx.x, nt);
+  if (t >= nt) return;
+  const int pair = blockIdx.y;
+  search_tile<R>(g, s, fr.f[pair], fr.f[pair + 1], t, recs + (size_t)pair * g.nb,
+                 ovf + (size_t)pair * g.nb * ovf_stride(s.p), slack, win, red, n_keep);
+}
+
+// The batch form: items are (job, pair, tile), numbered like k_search_batch.
+template <int R>
+__global__ void __launch_bounds__(1024)
+k_search_batch_tile(const BatchJob* __restrict__ jobs, int njobs, uint32_t items) {
+  extern __shared__ uint32_t win[];
+  __shared__ uint32_t red[64];
+  __shared__ uint32_t n_keep[4];
+  const uint32_t it = (uint32_t)xcd_band(blockIdx.x, (int)items);
+  if (it >= items) return;
+  const int lane = threadIdx.x & 63;
+  const uint32_t first = lane < njobs ? jobs[lane].item0 : 0xFFFFFFFFu;
+  const int j = __builtin_amdgcn_readfirstlane(__popcll(__ballot(first <= it)) - 1);
+  const BatchJob& J = jobs[j];
+  const KGeom g = J.g;
+  const uint32_t nt = (uint32_t)g.nb >> 2;
+  const uint32_t local = it - J.item0;
+  const int pair = (int)(local / nt), t = (int)(local % nt);
+  search_tile<R>(g, J.s, J.frames[pair], J.frames[pair + 1], t, J.recs + (size_t)pair * g.nb,
+                 J.ovf + (size_t)pair * g.nb * ovf_stride(g.p), J.slack, win, red, n_keep);
 }
 
 // ---------------------------------------------------------------------------
@@ -1259,12 +1431,13 @@ k_half_prep(const KGeom g, const FramePtrs fr, int npairs, BlockRec* __restrict_
   }
 }
 
-// The resolves of every pair of one batch class: one workgroup per pair.
+// The resolves of every pair of a set of FSBM jobs: one workgroup per pair,
+// workgroup k resolving pair k + pair_base of the numbering by pair0.
 __global__ void __launch_bounds__(1024)
-k_resolve_batch(const BatchJob* __restrict__ jobs, int njobs) {
+k_resolve_batch(const BatchJob* __restrict__ jobs, int njobs, uint32_t pair_base) {
   extern __shared__ uint32_t st_lds[];
   __shared__ int shared[2];
-  const uint32_t wg = blockIdx.x;
+  const uint32_t wg = blockIdx.x + pair_base;
   int j = 0;
   for (int base = 0; base < njobs; base += 64) {  // jobs are sorted by pair0
     const int k = base + (int)(threadIdx.x & 63);
@@ -1330,11 +1503,47 @@ static int launch_search_nm(const KGeom& g, const SearchPlan& pl, const FramePtr
   return e == hipSuccess ? ACBM_OK : hip_fail(e, "launching the window search");
 }
 
+// Rows of the tiled search (register budget of four blocks' accumulators).
+#define ACBM_TILE_R_LIST(X) X(1) X(2) X(3) X(4) X(5) X(6)
+
+static int launch_search_tile(const KGeom& g, const SearchPlan& pl, const FramePtrs& fr,
+                              int npairs, BlockRec* recs, uint16_t* ovf, uint32_t slack,
+                              hipStream_t st) {
+  if (g.bw != 8 || g.bh != 8 || (g.bx & 1) || (g.by & 1))
+    return fail(ACBM_E_INVAL, "tiled search needs 8x8 blocks on an even grid");
+  const WindowShape s = window_shape<16, 16>(g.p, pl.R);
+  const int nt = g.nb >> 2;
+  const int grid_x = ((nt + 7) / 8) * 8;
+  dim3 grid(grid_x, npairs), block(pl.threads);
+  switch (pl.R) {
+#define ACBM_CASE(RR)                                                                      \
+  case RR: {                                                                               \
+    if (pl.lds_bytes > 64 * 1024)                                                          \
+      (void)hipFuncSetAttribute((const void*)k_search_tile<RR>,                            \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, pl.lds_bytes); \
+    ProfScope ps("search", st);                                                            \
+    hipLaunchKernelGGL((k_search_tile<RR>), grid, block, pl.lds_bytes, st, g, s, fr, recs, \
+                       ovf, slack);                                                        \
+    break;                                                                                 \
+  }
+    ACBM_TILE_R_LIST(ACBM_CASE)
+#undef ACBM_CASE
+    default:
+      return fail(ACBM_E_UNSUPPORTED, "no tiled search kernel for this row blocking");
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ACBM_OK : hip_fail(e, "launching the tiled window search");
+}
+
 template <bool kTable>
 static int launch_search_with(const KGeom& g, const SearchPlan& pl, const FramePtrs& fr,
                               int npairs, uint32_t* table, BlockRec* recs, uint16_t* ovf,
                               uint32_t slack, hipStream_t st) {
   if (!pl.R) return fail(ACBM_E_UNSUPPORTED, "search window does not fit in LDS");
+  if (pl.tile == 2) {
+    if (kTable) return fail(ACBM_E_INVAL, "a SAD table is searched one block per workgroup");
+    return launch_search_tile(g, pl, fr, npairs, recs, ovf, slack, st);
+  }
   if (g.bw == 16 && g.bh == 16)
     return launch_search_nm<16, 16, kTable>(g, pl, fr, npairs, table, recs, ovf, slack, st);
   if (g.bw == 16 && g.bh == 8)
@@ -1349,8 +1558,8 @@ static int launch_search_with(const KGeom& g, const SearchPlan& pl, const FrameP
 template <bool kTable>
 static int launch_search(const KGeom& g, const FramePtrs& fr, int npairs, uint32_t* table,
                          BlockRec* recs, uint16_t* ovf, uint32_t slack, hipStream_t st) {
-  return launch_search_with<kTable>(g, plan_search(g.bw, g.bh, g.p), fr, npairs, table, recs,
-                                    ovf, slack, st);
+  return launch_search_with<kTable>(g, kTable ? plan_search(g.bw, g.bh, g.p) : plan_fsbm_search(g),
+                                    fr, npairs, table, recs, ovf, slack, st);
 }
 
 int launch_search_plan(const KGeom& g, const SearchPlan& pl, const uint8_t* const* frames,
@@ -1387,10 +1596,37 @@ static int launch_search_batch_nm(const SearchPlan& pl, size_t lds, const BatchJ
   return e == hipSuccess ? ACBM_OK : hip_fail(e, "launching the batched window search");
 }
 
+static int launch_search_batch_tile(const SearchPlan& pl, size_t lds, const BatchJob* jobs,
+                                    int njobs, uint32_t items, hipStream_t st) {
+  const int grid = (int)(((uint64_t)items + 7) / 8 * 8);
+  switch (pl.R) {
+#define ACBM_CASE(RR)                                                                        \
+  case RR: {                                                                                 \
+    if (lds > 64 * 1024)                                                                     \
+      (void)hipFuncSetAttribute((const void*)k_search_batch_tile<RR>,                        \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);       \
+    ProfScope ps("search", st);                                                              \
+    hipLaunchKernelGGL((k_search_batch_tile<RR>), dim3(grid), dim3(pl.threads), lds, st,     \
+                       jobs, njobs, items);                                                  \
+    break;                                                                                   \
+  }
+    ACBM_TILE_R_LIST(ACBM_CASE)
+#undef ACBM_CASE
+    default:
+      return fail(ACBM_E_UNSUPPORTED, "no tiled search kernel for this row blocking");
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ACBM_OK : hip_fail(e, "launching the batched tiled window search");
+}
+
 int launch_search_batch(int N, int M, const SearchPlan& pl, size_t lds, const BatchJob* jobs,
                         int njobs, uint32_t items, hipStream_t st) {
   if (!items) return ACBM_OK;
   if (njobs > 64) return fail(ACBM_E_INVAL, "more than 64 jobs in one search group");
+  if (pl.tile == 2) {
+    if (N != 8 || M != 8) return fail(ACBM_E_INVAL, "tiled search needs 8x8 blocks");
+    return launch_search_batch_tile(pl, lds, jobs, njobs, items, st);
+  }
   if (N == 16 && M == 16) return launch_search_batch_nm<16, 16>(pl, lds, jobs, njobs, items, st);
   if (N == 16 && M == 8) return launch_search_batch_nm<16, 8>(pl, lds, jobs, njobs, items, st);
   if (N == 8 && M == 16) return launch_search_batch_nm<8, 16>(pl, lds, jobs, njobs, items, st);
@@ -1398,14 +1634,14 @@ int launch_search_batch(int N, int M, const SearchPlan& pl, size_t lds, const Ba
   return fail(ACBM_E_UNSUPPORTED, "block size must be 8 or 16 in each direction");
 }
 
-int launch_resolve_batch(const BatchJob* jobs, int njobs, uint32_t pairs, size_t lds,
-                         hipStream_t st) {
+int launch_resolve_batch(const BatchJob* jobs, int njobs, uint32_t pair_base, uint32_t pairs,
+                         size_t lds, hipStream_t st) {
   if (!pairs) return ACBM_OK;
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute((const void*)k_resolve_batch,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   ProfScope ps("resolve", st);
-  hipLaunchKernelGGL(k_resolve_batch, dim3(pairs), dim3(1024), lds, st, jobs, njobs);
+  hipLaunchKernelGGL(k_resolve_batch, dim3(pairs), dim3(1024), lds, st, jobs, njobs, pair_base);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? ACBM_OK : hip_fail(e, "launching the batched resolve");
 }

@@ -55,8 +55,9 @@ struct WindowShape {
 };
 
 // One FSBM job of a batch as the batch kernels read it (device memory).
-// Search items are (pair, block) in pair-major order, numbered from item0
-// within the job's search group; resolve workgroups, one per pair, are
+// Search items are (pair, block) in pair-major order (with a tiled plan
+// (pair, 2x2 tile of blocks), and `s` is the tile's 16x16 window shape),
+// numbered from item0 within the job's search group; resolve workgroups, one per pair, are
 // numbered from pair0 across all FSBM jobs of the batch.
 struct BatchJob {
   KGeom g;
@@ -71,11 +72,14 @@ struct BatchJob {
   uint32_t subpel;               // half-pel precision (vectors in half-pel units)
 };
 
-// Launch plan of the window search for one (N, M, p).
+// Launch plan of the window search for one (N, M, p).  tile = 2: a
+// workgroup searches a 2x2 tile of 8x8 blocks over the tile's 16x16 window
+// (R, threads and lds_bytes are then those of the 16x16 window shape).
 struct SearchPlan {
   int R;        // candidate rows per lane
   int threads;  // workgroup size (multiple of 64, >= tasks)
   int lds_bytes;
+  int tile = 1;
 };
 
 // Workspace layout (all offsets 256-byte aligned).
@@ -105,16 +109,26 @@ int check_device();
 
 // The window shape the search kernels use for (N, M, p, R).
 WindowShape window_shape_host(int N, int M, int p, int R);
+// Plan of the one-block-per-workgroup search (SAD tables, statistics, and
+// FSBM where 2x2 tiles do not apply).
 SearchPlan plan_search(int N, int M, int p, int max_threads = 1024);
-// Plans by the cost model only (the candidates the autotuner times).
-SearchPlan plan_search_model(int N, int M, int p, int R);
-// Records a measured plan for (N, M, p); plan_search returns it from then on.
+// Whether the FSBM search of this geometry runs in 2x2 tiles of 8x8 blocks
+// (8x8 blocks, an even number of block columns and rows; ACBM_SEARCH_TILES=0
+// turns tiles off).
+bool tiles_apply(const KGeom& g);
+// The FSBM search plan of a geometry: tiled where tiles apply.
+SearchPlan plan_fsbm_search(const KGeom& g);
+// Plans by the cost model only (the candidates the autotuner times); tile 2
+// plans a 2x2 tile of 8x8 blocks (N = M = 8).
+SearchPlan plan_search_model(int N, int M, int p, int R, int tile = 1);
+// Records a measured plan for (N, M, p, tile); the planners return it from
+// then on.
 void set_tuned_plan(int N, int M, int p, const SearchPlan& pl);
 // The same, also appended to the tuning cache file (ACBM_TUNE_CACHE) with its
 // measured time per pair, when that variable names one.
 void save_tuned_plan(int N, int M, int p, const SearchPlan& pl, float ms);
-// A plan for (N, M, p) read from the tuning cache file, with its time.
-bool cached_plan(int N, int M, int p, SearchPlan* pl, float* ms);
+// A plan for (N, M, p, tile) read from the tuning cache file, with its time.
+bool cached_plan(int N, int M, int p, int tile, SearchPlan* pl, float* ms);
 
 // Brackets one kernel launch with timing events when profiling is on
 // (acbm_profile_enable); a no-op otherwise.
@@ -156,8 +170,9 @@ size_t fsbm_ovf_entries(int p);  // u16 entries of one block's overflow region
 size_t fsbm_mv_offset(const KGeom& g, uint32_t npairs);  // resolve state, if used
 bool fsbm_mv_in_lds(const KGeom& g);
 // Batch kernels: the full search of one group (at most 64 jobs with the
-// same N, M and plan; one workgroup per item) and the resolve of every pair
-// of a set of FSBM jobs (one workgroup per pair).
+// same N, M and plan; one workgroup per item: a block, or a 2x2 tile of 8x8
+// blocks with a tiled plan) and the resolve of every pair of a set of FSBM
+// jobs (one workgroup per pair).
 int launch_search_batch(int N, int M, const SearchPlan& pl, size_t lds, const BatchJob* jobs,
                         int njobs, uint32_t items, hipStream_t s);
 // Creates the current device's side streams for batch walker launches.
@@ -172,8 +187,10 @@ int noalloc_scratch_init();
 int batch_enqueue(const acbm_job* jobs, size_t njobs, const acbm_mv* const* prev0, void* ws,
                   size_t ws_bytes, hipStream_t st, bool side_streams,
                   std::vector<const uint32_t*>* status_words);
-int launch_resolve_batch(const BatchJob* jobs, int njobs, uint32_t pairs, size_t lds,
-                         hipStream_t s);
+// Resolves pairs pair_base .. pair_base + pairs - 1 (numbered by pair0) of
+// the `njobs` jobs at `jobs`, which must hold every job with such a pair.
+int launch_resolve_batch(const BatchJob* jobs, int njobs, uint32_t pair_base, uint32_t pairs,
+                         size_t lds, hipStream_t s);
 size_t predictive_ws_bytes(const KGeom& g, uint32_t npairs);
 int launch_predictive(const KGeom& g, const acbm_params& prm, int algo,
                       const uint8_t* const* frames, uint32_t npairs, const acbm_mv* prev_field,

@@ -925,15 +925,19 @@ static int launch_pred_nm(const PredLaunch& L, int R, int nt, bool hp, hipStream
 // 16x16 group (36 sequences) 4.9 against 5.3.  One sequence is bound by its
 // dependency chain instead, and its critical searches want the larger
 // walkers (1920x1088 p = 32, 59 pairs: 10.8 ms with 128 threads against 6.9
-// with 256).  So groups of at least four jobs take 128 threads.
+// with 256).  Many jobs of one pair each (a served pass: up to 15 requests
+// of 640x480 to 3840x2160 at p = 16-64) have only one pair's rows per job
+// and are chain-bound like one sequence: 1,930 requests/s saturated with 256
+// threads against 1,130 with 128.  So groups of at least four jobs with at
+// least four pairs per job on average take 128 threads.
 // ACBM_ROW_THREADS (128, 256 or 512) overrides.
-static int row_threads(int njobs) {
+static int row_threads(int njobs, double mean_pairs) {
   const char* e = std::getenv("ACBM_ROW_THREADS");
-  if (e) {
+  if (e && *e) {
     const int v = std::atoi(e);
     return (v == 128 || v == 512) ? v : 256;
   }
-  return njobs >= 4 ? 128 : 256;
+  return njobs >= 4 && mean_pairs >= 4.0 ? 128 : 256;
 }
 
 // Row blocking R of the critical search.  When a launch has more block rows
@@ -982,7 +986,10 @@ int plan_predictive_group(const KGeom* geoms, int n, bool hp, size_t total_rows,
   int imax = 0;  // the largest window decides which row blockings fit in LDS
   for (int i = 1; i < n; ++i)
     if (geoms[i].p > geoms[imax].p) imax = i;
-  pl->threads = hp ? 256 : row_threads(n);
+  size_t rows_per_pair = 0;  // block rows of one pair of every job
+  for (int i = 0; i < n; ++i) rows_per_pair += (size_t)geoms[i].by;
+  const double mean_pairs = rows_per_pair ? (double)total_rows / (double)rows_per_pair : 0.0;
+  pl->threads = hp ? 256 : row_threads(n, mean_pairs);
   pl->R = pick_rows(geoms[imax], pl->threads, total_rows, hp);
   if (!pl->R) return fail(ACBM_E_UNSUPPORTED, "search window too large for the predictive kernel");
   pl->lds = 0;

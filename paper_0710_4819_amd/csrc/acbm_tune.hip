@@ -1,7 +1,7 @@
 // acbm_tune.hip -- measured choice of the window-search plan.
 //
-// The cost model of plan_search ranks the row blockings R well but not
-// exactly (LDS bank conflicts, occupancy and the epilogue vary with R and
+// The cost model of the search planner ranks the row blockings R well but
+// not exactly (LDS bank conflicts, occupancy and the epilogue vary with R and
 // p); acbm_autotune times every candidate on the device instead and records
 // the fastest.  The search result never depends on R (every plan computes
 // the same exact SADs), so tuning only moves time.  With ACBM_TUNE_CACHE
@@ -53,9 +53,11 @@ extern "C" int acbm_autotune(const acbm_geom* g, uint32_t* best_rows, float* bes
   int rc = check_geom(g, &k);
   if (rc) return rc;
   if ((rc = check_device())) return rc;
+  // 8x8 blocks on an even grid of blocks search in 2x2 tiles: tune those
+  const int tile = tiles_apply(k) ? 2 : 1;
   SearchPlan cached{0, 0, 0};
   float cached_ms = 0;
-  if (cached_plan(k.bw, k.bh, k.p, &cached, &cached_ms)) {
+  if (cached_plan(k.bw, k.bh, k.p, tile, &cached, &cached_ms)) {
     // measured by an earlier process on this architecture: reuse it
     if (best_rows) *best_rows = (uint32_t)cached.R;
     if (best_ms) *best_ms = cached_ms;
@@ -83,7 +85,7 @@ extern "C" int acbm_autotune(const acbm_geom* g, uint32_t* best_rows, float* bes
   SearchPlan best{0, 0, 0};
   float best_t = 0;
   for (int R : {1, 2, 3, 4, 5, 6, 8, 11, 16}) {
-    const SearchPlan pl = plan_search_model(k.bw, k.bh, k.p, R);
+    const SearchPlan pl = plan_search_model(k.bw, k.bh, k.p, R, tile);
     if (!pl.R) continue;
     if ((rc = launch_search_plan(k, pl, fp, 1, recs, ovf, slack, st))) return rc;  // warm-up
     if ((e = hipEventRecord(ev.a, st)) != hipSuccess) return hip_fail(e, "timing");
