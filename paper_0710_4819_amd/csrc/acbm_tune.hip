@@ -80,14 +80,21 @@ extern "C" int acbm_autotune(const acbm_geom* g, uint32_t* best_rows, float* bes
   Events ev;
   if ((e = hipEventCreate(&ev.a)) != hipSuccess || (e = hipEventCreate(&ev.b)) != hipSuccess)
     return hip_fail(e, "creating autotune events");
-  // enough launches that small frames still time a few hundred microseconds
-  const int reps = std::max(3, std::min(200, 65536 / std::max(1, k.nb)));
   SearchPlan best{0, 0, 0};
   float best_t = 0;
   for (int R : {1, 2, 3, 4, 5, 6, 8, 11, 16}) {
     const SearchPlan pl = plan_search_model(k.bw, k.bh, k.p, R, tile);
     if (!pl.R) continue;
     if ((rc = launch_search_plan(k, pl, fp, 1, recs, ovf, slack, st))) return rc;  // warm-up
+    // one timed launch sizes the run: enough launches for about 3 ms, so that a
+    // 20-microsecond search is not decided by the noise of three launches
+    float one = 0;
+    if ((e = hipEventRecord(ev.a, st)) != hipSuccess) return hip_fail(e, "timing");
+    if ((rc = launch_search_plan(k, pl, fp, 1, recs, ovf, slack, st))) return rc;
+    if ((e = hipEventRecord(ev.b, st)) != hipSuccess) return hip_fail(e, "timing");
+    if ((e = hipEventSynchronize(ev.b)) != hipSuccess) return hip_fail(e, "timing");
+    if ((e = hipEventElapsedTime(&one, ev.a, ev.b)) != hipSuccess) return hip_fail(e, "timing");
+    const int reps = std::max(5, std::min(200, (int)(3.0f / std::max(one, 1e-3f))));
     if ((e = hipEventRecord(ev.a, st)) != hipSuccess) return hip_fail(e, "timing");
     for (int i = 0; i < reps; ++i)
       if ((rc = launch_search_plan(k, pl, fp, 1, recs, ovf, slack, st))) return rc;
