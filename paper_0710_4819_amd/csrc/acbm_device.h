@@ -199,7 +199,44 @@ __host__ __device__ inline WindowShape window_shape(int p, int R) {
   s.stride = s.dws | 1;  // odd stride spreads row starts over the LDS banks
   s.qmagic = (uint32_t)(((1ull << 32) + (uint64_t)s.quads - 1) / (uint64_t)s.quads);
   s.dmagic = (uint32_t)(((1ull << 32) + (uint64_t)s.dws - 1) / (uint64_t)s.dws);
+  const int iq = s.quads - (s.u_lo < -p ? 1 : 0) - (s.u_lo + 4 * s.quads - 1 > p ? 1 : 0);
+  s.imagic = iq > 1 ? (uint32_t)(((1ull << 32) + (uint64_t)iq - 1) / (uint64_t)iq) : 0u;
   return s;
+}
+
+// Lane t's task of a window search: quad q, row group gi.  The tasks that
+// hold padding candidates (a first quad reaching below -p, a last quad
+// beyond +p, a last row group beyond +p; `edge`) take the highest lane
+// numbers, after the interior tasks in row-group-major order: for a block
+// whose whole window is valid only the waves holding edge tasks mask
+// anything.  Every interior candidate has |u|, |v| <= p.
+template <int R>
+__device__ __forceinline__ void task_of(const WindowShape& s, int t, int* q, int* gi,
+                                        bool* edge) {
+  const int p = s.p;
+  const int q_lo = s.u_lo < -p ? 1 : 0;
+  const int q_hi = s.u_lo + 4 * s.quads - 1 > p ? 1 : 0;
+  const int g_hi = s.groups * R > 2 * p + 1 ? 1 : 0;
+  const int iq = s.quads - q_lo - q_hi;
+  const int interior = iq * (s.groups - g_hi);
+  if (t < interior) {
+    // t / iq (the magic of iq = 1 would be 2^32, which a u32 cannot hold)
+    const int g = iq == 1 ? t : (int)__umulhi((uint32_t)t, s.imagic);
+    *gi = g;
+    *q = q_lo + (t - g * iq);
+    *edge = false;
+    return;
+  }
+  const int e = t - interior, ncol = q_lo + q_hi;
+  *edge = true;
+  if (e < ncol * s.groups) {  // the padding quads, over every row group
+    const int c = ncol == 2 ? (e & 1) : 0;
+    *gi = ncol == 2 ? (e >> 1) : e;
+    *q = (c == 0 && q_lo) ? 0 : s.quads - 1;
+  } else {  // the padding row group's interior quads
+    *gi = s.groups - 1;
+    *q = q_lo + (e - ncol * s.groups);
+  }
 }
 
 // Cooperative load of the window into LDS (all threads of the group).  The

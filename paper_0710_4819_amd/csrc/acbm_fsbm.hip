@@ -126,21 +126,23 @@ __device__ __forceinline__ void search_block(const KGeom& g, const WindowShape& 
   const int tasks = s.quads * s.groups;
   const int t = threadIdx.x;
   const bool active = t < tasks;
-  const int gi = active ? (int)__umulhi((uint32_t)t, s.qmagic) : 0;  // t / quads
-  const int q = active ? t - gi * s.quads : 0;
+  int q = 0, gi = 0;
+  bool edge = false;
+  if (active) task_of<R>(s, t, &q, &gi, &edge);
   uint64_t acc[R];
   if (active) task_sads<N, M, R>(win, s.stride, q, gi, cb, acc);
 
   const int u0 = s.u_lo + 4 * q, v0 = -p + R * gi;
   // invalid candidates (outside the frame, or the padding of the quads and
-  // row groups beyond +-p) read as 0xFFFF from here on
+  // row groups beyond +-p) read as 0xFFFF from here on; a block whose whole
+  // window is valid has them in its edge tasks only
   const ValidBox vbox = valid_box(p, x0, y0, N, M, g.width, g.height);
   const bool whole = vbox.u_min == -p && vbox.u_max == p && vbox.v_min == -p && vbox.v_max == p;
   if (active) {
-    if (whole)
-      mask_padding<R>(acc, p, u0, v0);
-    else
+    if (!whole)
       mask_invalid<R>(acc, vbox, u0, v0);
+    else if (edge)
+      mask_padding<R>(acc, p, u0, v0);
   }
 
   if (K == kKindStats) {
@@ -321,7 +323,8 @@ k_search_batch(const BatchJob* __restrict__ jobs, int njobs, uint32_t items) {
 // region.  Against four workgroups of one block each, the tile loads one
 // 80x80 window instead of four 72x72 ones (p = 32), reads fewer LDS dwords
 // per QSAD and pays the per-workgroup costs once.  `t` is the tile index in
-// the frame's grid of (bx/2) x (by/2) tiles; `recs` and `ovf` are the pair's.
+// the frame's grid of (bx/2) x (by/2) tiles; `recs` and `ovf` are the pair's;
+// `intra` is 4 words of LDS.
 // ---------------------------------------------------------------------------
 template <int R>
 __device__ __forceinline__ void search_tile(const KGeom& g, const WindowShape& s,
@@ -329,7 +332,8 @@ __device__ __forceinline__ void search_tile(const KGeom& g, const WindowShape& s
                                             const uint8_t* __restrict__ cur, int t,
                                             BlockRec* __restrict__ recs,
                                             uint16_t* __restrict__ ovf, uint32_t slack,
-                                            uint32_t* win, uint32_t* red, uint32_t* n_keep) {
+                                            uint32_t* win, uint32_t* red, uint32_t* n_keep,
+                                            uint32_t* intra) {
   const int tbx = g.bx >> 1;
   const int tr = t / tbx, tc = t - tr * tbx;
   const int x0 = tc * 16, y0 = tr * 16;
@@ -338,11 +342,13 @@ __device__ __forceinline__ void search_tile(const KGeom& g, const WindowShape& s
   load_window<16, 16>(win, s, ref, g.pitch, g.width, g.height, x0, y0);
   CurBlock<16, 16> cb;
   load_cur_uniform<16, 16>(cb, cur, g.pitch, x0, y0);
-  uint32_t intra[4] = {0, 0, 0, 0};
-  if (threadIdx.x < 64) {
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-      intra[b] = wave_intra_x<8, 8>(cur, g.pitch, x0 + 8 * (b & 1), y0 + 8 * (b >> 1));
+  // IntraX of the four blocks, spread over the waves (block b by wave b mod waves)
+  {
+    const int wv = threadIdx.x >> 6, nwv = (blockDim.x + 63) >> 6;
+    for (int b = wv; b < 4; b += nwv) {
+      const uint32_t ix = wave_intra_x<8, 8>(cur, g.pitch, x0 + 8 * (b & 1), y0 + 8 * (b >> 1));
+      if ((threadIdx.x & 63) == 0) intra[b] = ix;
+    }
   }
   if (threadIdx.x < 4) n_keep[threadIdx.x] = 0;
   __syncthreads();
@@ -350,8 +356,9 @@ __device__ __forceinline__ void search_tile(const KGeom& g, const WindowShape& s
   const int tasks = s.quads * s.groups;
   const int th = threadIdx.x;
   const bool active = th < tasks;
-  const int gi = active ? (int)__umulhi((uint32_t)th, s.qmagic) : 0;  // th / quads
-  const int q = active ? th - gi * s.quads : 0;
+  int q = 0, gi = 0;
+  bool edge = false;
+  if (active) task_of<R>(s, th, &q, &gi, &edge);
   uint64_t acc[4][R];
   if (active) task_sads_tile<R>(win, s.stride, q, gi, cb, acc);
 
@@ -363,10 +370,10 @@ __device__ __forceinline__ void search_tile(const KGeom& g, const WindowShape& s
         valid_box(p, x0 + 8 * (b & 1), y0 + 8 * (b >> 1), 8, 8, g.width, g.height);
     const bool whole = vbox.u_min == -p && vbox.u_max == p && vbox.v_min == -p && vbox.v_max == p;
     if (active) {
-      if (whole)
-        mask_padding<R>(acc[b], p, u0, v0);
-      else
+      if (!whole)
         mask_invalid<R>(acc[b], vbox, u0, v0);
+      else if (edge)
+        mask_padding<R>(acc[b], p, u0, v0);
     }
     lmin[b] = active ? min_u16_lanes<R>(acc[b]) : 0xFFFFu;
   }
@@ -453,12 +460,13 @@ k_search_tile(const KGeom g, const WindowShape s, const FramePtrs fr, BlockRec* 
   extern __shared__ uint32_t win[];
   __shared__ uint32_t red[64];
   __shared__ uint32_t n_keep[4];
+  __shared__ uint32_t intra[4];
   const int nt = g.nb >> 2;
   const int t = xcd_band(blockIdx.x, nt);
   if (t >= nt) return;
   const int pair = blockIdx.y;
   search_tile<R>(g, s, fr.f[pair], fr.f[pair + 1], t, recs + (size_t)pair * g.nb,
-                 ovf + (size_t)pair * g.nb * ovf_stride(s.p), slack, win, red, n_keep);
+                 ovf + (size_t)pair * g.nb * ovf_stride(s.p), slack, win, red, n_keep, intra);
 }
 
 // The batch form: items are (job, pair, tile), numbered like k_search_batch.
@@ -468,6 +476,7 @@ k_search_batch_tile(const BatchJob* __restrict__ jobs, int njobs, uint32_t items
   extern __shared__ uint32_t win[];
   __shared__ uint32_t red[64];
   __shared__ uint32_t n_keep[4];
+  __shared__ uint32_t intra[4];
   const uint32_t it = (uint32_t)xcd_band(blockIdx.x, (int)items);
   if (it >= items) return;
   const int lane = threadIdx.x & 63;
@@ -479,7 +488,7 @@ k_search_batch_tile(const BatchJob* __restrict__ jobs, int njobs, uint32_t items
   const uint32_t local = it - J.item0;
   const int pair = (int)(local / nt), t = (int)(local % nt);
   search_tile<R>(g, J.s, J.frames[pair], J.frames[pair + 1], t, J.recs + (size_t)pair * g.nb,
-                 J.ovf + (size_t)pair * g.nb * ovf_stride(g.p), J.slack, win, red, n_keep);
+                 J.ovf + (size_t)pair * g.nb * ovf_stride(g.p), J.slack, win, red, n_keep, intra);
 }
 
 // ---------------------------------------------------------------------------

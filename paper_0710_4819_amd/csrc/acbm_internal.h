@@ -50,8 +50,9 @@ struct WindowShape {
   int dws;     // dwords per LDS row (>= quads + N/4)
   int stride;  // LDS row stride in dwords
   // ceil(2^32 / quads) and ceil(2^32 / dws): t / d == umulhi(t, magic)
-  // exactly for every t < 2^16 and d < 2^8 (checked exhaustively)
-  uint32_t qmagic, dmagic;
+  // exactly for every t < 2^16 and d < 2^8 (checked exhaustively); imagic the
+  // same for the quads that hold no padding candidate (see task_of)
+  uint32_t qmagic, dmagic, imagic;
 };
 
 // One FSBM job of a batch as the batch kernels read it (device memory).
