@@ -91,9 +91,9 @@ __device__ __forceinline__ uint32_t wave_intra_x(const uint8_t* __restrict__ cur
 // depends on the kind K:
 //  kKindTable  the block's u32 table `tab`;
 //  kKindFsbm   its BlockRec `rec` (SAD minimum, the number of candidates that
-//              can still win and the first kShort of them) and, when more
-//              than kShort can win, its overflow region `row`: the list of
-//              all of them while it fits (ovf_list_cap entries), else the
+//              can still win and, when at most kShort can, those candidates)
+//              and, when more can win, its overflow region `row`: the list
+//              of all of them while it fits (ovf_list_cap entries), else the
 //              whole row of SADs;
 //  kKindStats  its statistics `bst`: SAD minimum, valid count,
 //              SAD_deviation and IntraX (Section 3.1).
@@ -206,33 +206,39 @@ __device__ __forceinline__ void search_block(const KGeom& g, const WindowShape& 
   const uint32_t smin = group_min_u32(lmin, reinterpret_cast<uint32_t*>(red));
   const uint32_t thr = (uint32_t)min<uint64_t>((uint64_t)smin + slack, 0xFFFEu);
 
-  if (active && lmin <= thr) {  // rare: this lane holds a possible winner
+  // Count this lane's possible winners and reserve their slots; once the
+  // block's total is known, write each entry once, where the resolve will
+  // read it: the record (at most kShort), the overflow list (at most cap),
+  // or, beyond that, the whole row of SADs.
+  const bool any = active && lmin <= thr;
+  uint32_t slot = 0;
+  if (any) {
     uint32_t mine = 0;
 #pragma unroll
     for (int rr = 0; rr < R; ++rr)
 #pragma unroll
       for (int i = 0; i < 4; ++i) mine += ((uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu) <= thr;
-    uint32_t slot = atomicAdd(n_keep, mine);
-    const uint32_t cap = ovf_list_cap(p);
-    uint32_t* __restrict__ list = reinterpret_cast<uint32_t*>(row);
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const uint32_t sad = (uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu;
-        if (sad <= thr) {
-          const uint32_t e = (sad << 16) | (uint32_t)((v0 + rr + p) * W + (u0 + i + p));
-          if (slot < (uint32_t)kShort) rec->e[slot] = e;
-          if (slot < cap) list[slot] = e;  // used when kShort < total <= cap
-          ++slot;
-        }
-      }
+    slot = atomicAdd(n_keep, mine);
   }
   __syncthreads();
   const uint32_t total = *n_keep;
-  // more candidates than the list holds: the whole row of SADs instead
-  // (written after the barrier, so it replaces any list entries)
-  if (total > ovf_list_cap(p) && active) {
+  // (at small p the list holds fewer than kShort: the record takes up to kShort)
+  if (total <= (uint32_t)kShort || total <= ovf_list_cap(p)) {
+    if (any) {
+      uint32_t* __restrict__ dst =
+          total <= (uint32_t)kShort ? rec->e : reinterpret_cast<uint32_t*>(row);
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t sad = (uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu;
+          if (sad <= thr) {
+            dst[slot] = (sad << 16) | (uint32_t)((v0 + rr + p) * W + (u0 + i + p));
+            ++slot;
+          }
+        }
+    }
+  } else if (active) {
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
       const int v = v0 + rr;
@@ -394,32 +400,24 @@ __device__ __forceinline__ void search_tile(const KGeom& g, const WindowShape& s
     smin[b] = m;
   }
 
+  // per block as in search_block: count and reserve, then write each entry
+  // once where the resolve reads it
   const uint32_t cap = ovf_list_cap(p);
+  uint32_t thr[4], slot[4];
+  bool any[4];
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
-    const uint32_t thr = (uint32_t)min<uint64_t>((uint64_t)smin[b] + slack, 0xFFFEu);
-    if (active && lmin[b] <= thr) {  // rare: this lane holds a possible winner of block b
-      const int blk = (2 * tr + (b >> 1)) * g.bx + 2 * tc + (b & 1);
-      BlockRec* __restrict__ rec = recs + blk;
-      uint32_t* __restrict__ list = reinterpret_cast<uint32_t*>(ovf + (size_t)blk * ovf_stride(p));
+    thr[b] = (uint32_t)min<uint64_t>((uint64_t)smin[b] + slack, 0xFFFEu);
+    any[b] = active && lmin[b] <= thr[b];
+    slot[b] = 0;
+    if (any[b]) {
       uint32_t mine = 0;
 #pragma unroll
       for (int rr = 0; rr < R; ++rr)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) mine += ((uint32_t)(acc[b][rr] >> (16 * i)) & 0xFFFFu) <= thr;
-      uint32_t slot = atomicAdd(&n_keep[b], mine);
-#pragma unroll
-      for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const uint32_t sad = (uint32_t)(acc[b][rr] >> (16 * i)) & 0xFFFFu;
-          if (sad <= thr) {
-            const uint32_t e = (sad << 16) | (uint32_t)((v0 + rr + p) * W + (u0 + i + p));
-            if (slot < (uint32_t)kShort) rec->e[slot] = e;
-            if (slot < cap) list[slot] = e;  // used when kShort < total <= cap
-            ++slot;
-          }
-        }
+        for (int i = 0; i < 4; ++i)
+          mine += ((uint32_t)(acc[b][rr] >> (16 * i)) & 0xFFFFu) <= thr[b];
+      slot[b] = atomicAdd(&n_keep[b], mine);
     }
   }
   __syncthreads();
@@ -428,9 +426,23 @@ __device__ __forceinline__ void search_tile(const KGeom& g, const WindowShape& s
     const uint32_t total = n_keep[b];
     const int blk = (2 * tr + (b >> 1)) * g.bx + 2 * tc + (b & 1);
     uint16_t* __restrict__ row = ovf + (size_t)blk * ovf_stride(p);
-    // more candidates than the list holds: the whole row of SADs instead
-    // (written after the barrier, so it replaces any list entries)
-    if (total > cap && active) {
+    if (total <= (uint32_t)kShort || total <= cap) {
+      if (any[b]) {
+        uint32_t* __restrict__ dst =
+            total <= (uint32_t)kShort ? recs[blk].e : reinterpret_cast<uint32_t*>(row);
+        uint32_t sl = slot[b];
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const uint32_t sad = (uint32_t)(acc[b][rr] >> (16 * i)) & 0xFFFFu;
+            if (sad <= thr[b]) {
+              dst[sl] = (sad << 16) | (uint32_t)((v0 + rr + p) * W + (u0 + i + p));
+              ++sl;
+            }
+          }
+      }
+    } else if (active) {
 #pragma unroll
       for (int rr = 0; rr < R; ++rr) {
         const int v = v0 + rr;

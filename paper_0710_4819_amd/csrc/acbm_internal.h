@@ -21,10 +21,11 @@ struct KGeom {
 // Per-block record written by the full-search pass for the FSBM resolve:
 // the block's SAD minimum, how many candidates can still win (their SAD is
 // within lambda*(Rmax-2) of the minimum, see the pruning bound in the
-// resolve kernel), IntraX, and up to kShort of those candidates packed as
-// (SAD << 16 | window raster index).  When more than kShort can win, the
-// block's overflow region holds all of them in the same packing, or, if
-// even that does not fit, the block's whole row of SADs.
+// resolve kernel), IntraX, and, when at most kShort can win, those
+// candidates packed as (SAD << 16 | window raster index).  When more can
+// win, the record's list is unused and the block's overflow region holds
+// all of them in the same packing, or, if even that does not fit, the
+// block's whole row of SADs.
 constexpr int kShort = 28;
 struct BlockRec {
   uint32_t sad_min, count, intra_x, pad;
