@@ -348,13 +348,22 @@ __device__ __forceinline__ void search_tile(const KGeom& g, const WindowShape& s
   load_window<16, 16>(win, s, ref, g.pitch, g.width, g.height, x0, y0);
   CurBlock<16, 16> cb;
   load_cur_uniform<16, 16>(cb, cur, g.pitch, x0, y0);
-  // IntraX of the four blocks, spread over the waves (block b by wave b mod waves)
-  {
-    const int wv = threadIdx.x >> 6, nwv = (blockDim.x + 63) >> 6;
-    for (int b = wv; b < 4; b += nwv) {
-      const uint32_t ix = wave_intra_x<8, 8>(cur, g.pitch, x0 + 8 * (b & 1), y0 + 8 * (b >> 1));
-      if ((threadIdx.x & 63) == 0) intra[b] = ix;
+  // IntraX of the four blocks in one pass of wave 0: lanes 16b .. 16b+15 hold
+  // block b's 16 dwords (row k/2, dword k%2 for lane 16b + k), and both sums
+  // are sums over those 16 lanes
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x, b = lane >> 4, k = lane & 15;
+    const uint32_t d = *reinterpret_cast<const uint32_t*>(
+        cur + (size_t)(y0 + 8 * (b >> 1) + (k >> 1)) * g.pitch + x0 + 8 * (b & 1) + 4 * (k & 1));
+    const uint32_t sum = group_sum<16>(__builtin_amdgcn_sad_u8(d, 0u, 0u));
+    uint32_t a = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = 64 * (int)((d >> (8 * q)) & 0xFF) - (int)sum;
+      a += (uint32_t)(e < 0 ? -e : e);
     }
+    a = group_sum<16>(a);
+    if (k == 0) intra[b] = a;
   }
   if (threadIdx.x < 4) n_keep[threadIdx.x] = 0;
   __syncthreads();
