@@ -100,6 +100,38 @@ __device__ __forceinline__ uint32_t wave_intra_x(const uint8_t* __restrict__ cur
 // `win` is the window in LDS, `red` one slot per wave, `n_keep` a shared
 // counter.
 // ---------------------------------------------------------------------------
+// The candidates of a task that can still win (SAD <= thr), as bits 4*rr + i.
+template <int R>
+__device__ __forceinline__ uint64_t keep_mask(const uint64_t (&acc)[R], uint32_t thr) {
+  static_assert(4 * R <= 64, "a task's candidates fit the mask");
+  uint64_t m = 0;
+#pragma unroll
+  for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      m |= (uint64_t)(((uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu) <= thr) << (4 * rr + i);
+  return m;
+}
+
+// Stores the kept candidates of a task at dst[slot], dst[slot + 1], ... as
+// (SAD << 16 | window raster index): one loop turn per kept candidate, the
+// candidate's accumulator picked by a select chain (no dynamic register index).
+template <int R>
+__device__ __forceinline__ void write_kept(const uint64_t (&acc)[R], uint64_t keep, uint32_t slot,
+                                           uint32_t* __restrict__ dst, int u0, int v0, int p,
+                                           int W) {
+  while (keep) {
+    const int j = __builtin_ctzll(keep);
+    keep &= keep - 1;
+    const int rr = j >> 2, i = j & 3;
+    uint64_t a = acc[0];
+#pragma unroll
+    for (int r = 1; r < R; ++r) a = rr == r ? acc[r] : a;
+    const uint32_t sad = (uint32_t)(a >> (16 * i)) & 0xFFFFu;
+    dst[slot++] = (sad << 16) | (uint32_t)((v0 + rr + p) * W + (u0 + i + p));
+  }
+}
+
 enum : int { kKindFsbm = 0, kKindTable = 1, kKindStats = 2 };
 
 template <int N, int M, int R, int K>
@@ -211,33 +243,20 @@ __device__ __forceinline__ void search_block(const KGeom& g, const WindowShape& 
   // read it: the record (at most kShort), the overflow list (at most cap),
   // or, beyond that, the whole row of SADs.
   const bool any = active && lmin <= thr;
+  uint64_t keep = 0;  // bit 4*rr + i: candidate (u0 + i, v0 + rr) can still win
   uint32_t slot = 0;
   if (any) {
-    uint32_t mine = 0;
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) mine += ((uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu) <= thr;
-    slot = atomicAdd(n_keep, mine);
+    keep = keep_mask<R>(acc, thr);
+    slot = atomicAdd(n_keep, (uint32_t)__popcll(keep));
   }
   __syncthreads();
   const uint32_t total = *n_keep;
   // (at small p the list holds fewer than kShort: the record takes up to kShort)
   if (total <= (uint32_t)kShort || total <= ovf_list_cap(p)) {
-    if (any) {
-      uint32_t* __restrict__ dst =
-          total <= (uint32_t)kShort ? rec->e : reinterpret_cast<uint32_t*>(row);
-#pragma unroll
-      for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const uint32_t sad = (uint32_t)(acc[rr] >> (16 * i)) & 0xFFFFu;
-          if (sad <= thr) {
-            dst[slot] = (sad << 16) | (uint32_t)((v0 + rr + p) * W + (u0 + i + p));
-            ++slot;
-          }
-        }
-    }
+    if (keep)
+      write_kept<R>(acc, keep, slot,
+                    total <= (uint32_t)kShort ? rec->e : reinterpret_cast<uint32_t*>(row), u0,
+                    v0, p, W);
   } else if (active) {
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
@@ -412,21 +431,16 @@ __device__ __forceinline__ void search_tile(const KGeom& g, const WindowShape& s
   // per block as in search_block: count and reserve, then write each entry
   // once where the resolve reads it
   const uint32_t cap = ovf_list_cap(p);
-  uint32_t thr[4], slot[4];
-  bool any[4];
+  uint64_t keep[4];
+  uint32_t slot[4];
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
-    thr[b] = (uint32_t)min<uint64_t>((uint64_t)smin[b] + slack, 0xFFFEu);
-    any[b] = active && lmin[b] <= thr[b];
+    const uint32_t thr = (uint32_t)min<uint64_t>((uint64_t)smin[b] + slack, 0xFFFEu);
+    keep[b] = 0;
     slot[b] = 0;
-    if (any[b]) {
-      uint32_t mine = 0;
-#pragma unroll
-      for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          mine += ((uint32_t)(acc[b][rr] >> (16 * i)) & 0xFFFFu) <= thr[b];
-      slot[b] = atomicAdd(&n_keep[b], mine);
+    if (active && lmin[b] <= thr) {
+      keep[b] = keep_mask<R>(acc[b], thr);
+      slot[b] = atomicAdd(&n_keep[b], (uint32_t)__popcll(keep[b]));
     }
   }
   __syncthreads();
@@ -436,21 +450,10 @@ __device__ __forceinline__ void search_tile(const KGeom& g, const WindowShape& s
     const int blk = (2 * tr + (b >> 1)) * g.bx + 2 * tc + (b & 1);
     uint16_t* __restrict__ row = ovf + (size_t)blk * ovf_stride(p);
     if (total <= (uint32_t)kShort || total <= cap) {
-      if (any[b]) {
-        uint32_t* __restrict__ dst =
-            total <= (uint32_t)kShort ? recs[blk].e : reinterpret_cast<uint32_t*>(row);
-        uint32_t sl = slot[b];
-#pragma unroll
-        for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const uint32_t sad = (uint32_t)(acc[b][rr] >> (16 * i)) & 0xFFFFu;
-            if (sad <= thr[b]) {
-              dst[sl] = (sad << 16) | (uint32_t)((v0 + rr + p) * W + (u0 + i + p));
-              ++sl;
-            }
-          }
-      }
+      if (keep[b])
+        write_kept<R>(acc[b], keep[b], slot[b],
+                      total <= (uint32_t)kShort ? recs[blk].e : reinterpret_cast<uint32_t*>(row),
+                      u0, v0, p, W);
     } else if (active) {
 #pragma unroll
       for (int rr = 0; rr < R; ++rr) {
