@@ -376,7 +376,7 @@ int side_pool(int dev, SidePool** out) {
 }
 
 int enqueue_fsbm(const acbm_job* jobs, const Plan& pl, char* base, const BatchJob* all,
-                 hipStream_t st, hipStream_t rs, hipEvent_t searched);
+                 hipStream_t st, const hipStream_t* rs, int nrs, hipEvent_t searched);
 
 }  // namespace
 
@@ -429,12 +429,18 @@ int enqueue_batch(const acbm_job* jobs, size_t njobs, const acbm_mv* const* prev
   const bool has_fsbm = !pl.classes.empty();
   const size_t off_st = has_fsbm ? nunits : nunits - std::min<size_t>(nunits, 1);
   const bool resolve_side = pl.classes.size() > 1;
+  // resolve streams wanted: one for the first run of classes (the longest
+  // chain), and one for each later class, at most three (see enqueue_fsbm)
+  int runs_later = 0;
+  for (size_t i = 1; i < pl.classes.size(); ++i)
+    if (pl.classes[i].steps < pl.classes[0].steps) ++runs_later;
+  const int want_r = resolve_side ? 1 + std::min(runs_later, 3) : 0;
   std::unique_lock<std::mutex> lk(g_side_mu, std::defer_lock);
   SidePool* sp = nullptr;
   int nside = 0;
   const int want_w =
       allow_side ? std::min<int>(side_streams(), (int)std::min<size_t>(kSideStreams, off_st)) : 0;
-  int want = allow_side ? std::min<int>(side_streams(), want_w + (resolve_side ? 1 : 0)) : 0;
+  int want = allow_side ? std::min<int>(side_streams(), want_w + want_r) : 0;
   if (want > 0) {
     int cur = -1;
     hipDevice_t sdev = -1;
@@ -480,7 +486,12 @@ int enqueue_batch(const acbm_job* jobs, size_t njobs, const acbm_mv* const* prev
   const int nside_w = std::min(nside, want_w);  // side streams of walker launches
   // the resolve stream: a side stream of its own when one is left, else the
   // last walker stream
-  hipStream_t rs = resolve_side && nside > 0 ? sp->s[nside - 1] : nullptr;
+  hipStream_t rs[kSideStreams] = {};
+  int nrs = 0;
+  if (resolve_side && nside > 0) {
+    for (int i = nside_w; i < nside; ++i) rs[nrs++] = sp->s[i];
+    if (!nrs) rs[nrs++] = sp->s[nside - 1];  // shared with the last walker stream
+  }
   const int lanes = nside_w + (has_fsbm && nside_w ? 0 : 1);  // lane nside_w is `st`
   for (size_t u = 0; u < nunits && !rc; ++u) {
     const int lane = (int)(u % lanes);
@@ -504,7 +515,7 @@ int enqueue_batch(const acbm_job* jobs, size_t njobs, const acbm_mv* const* prev
                              prev0 ? prev0[i] : nullptr, base + pl.slice[i], b, j.out, su);
     }
   }
-  if (!rc) rc = enqueue_fsbm(jobs, pl, base, all, st, rs, rs ? sp->searched : nullptr);
+  if (!rc) rc = enqueue_fsbm(jobs, pl, base, all, st, rs, nrs, nrs ? sp->searched : nullptr);
   // join every forked stream, after an error too, so that a capture of `st`
   // still ends with every branch joined
   for (int i = 0; i < nside; ++i) {
@@ -521,7 +532,9 @@ int enqueue_batch(const acbm_job* jobs, size_t njobs, const acbm_mv* const* prev
 // caller), resolve launches on `rs` that start as soon as their groups are
 // searched.
 int enqueue_fsbm(const acbm_job* jobs, const Plan& pl, char* base, const BatchJob* all,
-                 hipStream_t st, hipStream_t rs, hipEvent_t searched) {
+                 hipStream_t st, const hipStream_t* rss, int nrs, hipEvent_t searched) {
+  hipStream_t rs = nrs ? rss[0] : nullptr;  // the first run's resolve stream
+  int next_rs = 0;                          // later classes rotate over the rest
   int rc = ACBM_OK;
   size_t jo = 0;
   size_t pend = 0, pend_jo = 0;  // first class (and its job) not yet resolved
@@ -566,22 +579,29 @@ int enqueue_fsbm(const acbm_job* jobs, const Plan& pl, char* base, const BatchJo
     // launch, so their pairs resolve side by side rather than one class
     // after the other on the stream); the classes sort by that chain, so
     // the long resolves overlap the searches of the classes after them.
+    // Classes after the first run resolve one launch each, as soon as each is
+    // searched, on the other resolve streams in turn (side by side, so that
+    // their chains do not add up): the last one's resolve alone is left after
+    // the searches.
     const size_t ci = (size_t)(&c - pl.classes.data());
-    if (rs && (ci + 1 == pl.classes.size() || pl.classes[ci + 1].steps < c.steps)) {
+    const bool first_run = c.steps == pl.classes[0].steps;
+    if (rs && (!first_run || ci + 1 == pl.classes.size() || pl.classes[ci + 1].steps < c.steps)) {
+      hipStream_t to = rs;
+      if (!first_run && nrs > 1) to = rss[1 + next_rs++ % (nrs - 1)];
       hipError_t e = hipEventRecord(searched, st);
-      if (e == hipSuccess) e = hipStreamWaitEvent(rs, searched, 0);
+      if (e == hipSuccess) e = hipStreamWaitEvent(to, searched, 0);
       if (e != hipSuccess) return hip_fail(e, "ordering a batch resolve after its search");
       const Class& c0 = pl.classes[pend];
       size_t lds = 0;
       for (size_t k = pend; k <= ci; ++k) lds = std::max(lds, pl.classes[k].lds_resolve);
       if ((rc = launch_resolve_batch(all + pend_jo, (int)(jo - pend_jo), c0.pair0,
-                                     c.pair0 + c.pairs - c0.pair0, lds, rs)))
+                                     c.pair0 + c.pairs - c0.pair0, lds, to)))
         return rc;
       pend = ci + 1;
       pend_jo = jo;
     }
   }
-  if (!rs && pl.njob_fsbm &&
+  if (!nrs && pl.njob_fsbm &&
       (rc = launch_resolve_batch(all, (int)pl.njob_fsbm, 0, pl.pairs, pl.lds_resolve, st)))
     return rc;
   return ACBM_OK;
