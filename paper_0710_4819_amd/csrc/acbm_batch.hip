@@ -75,6 +75,7 @@ struct Class {
   size_t lds_resolve = 0;  // the resolve of this class's pairs
   uint32_t pair0 = 0, pairs = 0;
   int steps = 0;           // longest anti-diagonal walk of its resolves, bx + 2(by - 1)
+  int max_by = 0;          // most block rows of its frames
 };
 
 struct Plan {
@@ -89,6 +90,7 @@ struct Plan {
   size_t njob_fsbm = 0, nptr = 0;
   uint32_t pairs = 0;             // FSBM pairs (resolve workgroups)
   size_t lds_resolve = 0;
+  int max_by = 0;
 };
 
 // Groups the jobs and lays out the workspace: job slices first, then the
@@ -171,6 +173,7 @@ int make_plan(const acbm_job* jobs, size_t njobs, Plan* pl) {
     c.lds_search = std::max<size_t>(c.lds_search, (size_t)sp.lds_bytes);
     if (fsbm_mv_in_lds(k)) c.lds_resolve = std::max<size_t>(c.lds_resolve, (size_t)k.nb * 4);
     c.steps = std::max(c.steps, k.bx + 2 * (k.by - 1));
+    c.max_by = std::max(c.max_by, k.by);
     c.jobs.push_back(bj);
     c.job_index.push_back(i);
     pl->njob_fsbm += 1;
@@ -189,6 +192,7 @@ int make_plan(const acbm_job* jobs, size_t njobs, Plan* pl) {
     }
     c.pairs = pl->pairs - c.pair0;
     pl->lds_resolve = std::max(pl->lds_resolve, c.lds_resolve);
+    pl->max_by = std::max(pl->max_by, c.max_by);
   }
   pl->jobs_bytes = off;
   pl->table_off = off;
@@ -593,16 +597,21 @@ int enqueue_fsbm(const acbm_job* jobs, const Plan& pl, char* base, const BatchJo
       if (e != hipSuccess) return hip_fail(e, "ordering a batch resolve after its search");
       const Class& c0 = pl.classes[pend];
       size_t lds = 0;
-      for (size_t k = pend; k <= ci; ++k) lds = std::max(lds, pl.classes[k].lds_resolve);
+      int max_by = 0;
+      for (size_t k = pend; k <= ci; ++k) {
+        lds = std::max(lds, pl.classes[k].lds_resolve);
+        max_by = std::max(max_by, pl.classes[k].max_by);
+      }
       if ((rc = launch_resolve_batch(all + pend_jo, (int)(jo - pend_jo), c0.pair0,
-                                     c.pair0 + c.pairs - c0.pair0, lds, to)))
+                                     c.pair0 + c.pairs - c0.pair0, lds, max_by, to)))
         return rc;
       pend = ci + 1;
       pend_jo = jo;
     }
   }
   if (!nrs && pl.njob_fsbm &&
-      (rc = launch_resolve_batch(all, (int)pl.njob_fsbm, 0, pl.pairs, pl.lds_resolve, st)))
+      (rc = launch_resolve_batch(all, (int)pl.njob_fsbm, 0, pl.pairs, pl.lds_resolve, pl.max_by,
+                                 st)))
     return rc;
   return ACBM_OK;
 }

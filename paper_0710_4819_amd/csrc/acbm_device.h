@@ -261,12 +261,12 @@ __device__ inline void load_window(uint32_t* __restrict__ win, const WindowShape
     if (r0 < per) {
 #pragma unroll 4
       for (int row = r0; row < main_rows; row += per)
-        win[row * s.stride + dw] = *reinterpret_cast<const uint32_t*>(base + (size_t)row * pitch);
+        win[row * s.stride + dw] = ld_global<uint32_t>(base + (size_t)row * pitch);
     }
     // the last rows % per rows: one per group of dws threads
     const int row = main_rows + r0;
     if (r0 < per && row < s.rows)
-      win[row * s.stride + dw] = *reinterpret_cast<const uint32_t*>(base + (size_t)row * pitch);
+      win[row * s.stride + dw] = ld_global<uint32_t>(base + (size_t)row * pitch);
   } else {
     const int x = xs + 4 * dw;
     const bool xok = x >= 0 && x + 3 < width;
@@ -274,7 +274,7 @@ __device__ inline void load_window(uint32_t* __restrict__ win, const WindowShape
       const int y = ys + row;
       uint32_t val = 0;
       if (xok && y >= 0 && y < height)
-        val = *reinterpret_cast<const uint32_t*>(ref + (size_t)y * pitch + x);
+        val = ld_global<uint32_t>(ref + (size_t)y * pitch + x);
       win[row * s.stride + dw] = val;
     }
   }
@@ -297,7 +297,7 @@ __device__ __forceinline__ void load_cur_uniform(CurBlock<N, M>& cb,
         reinterpret_cast<const uint32_t*>(cur + (size_t)(y0 + j) * pitch + x0);
 #pragma unroll
     for (int k = 0; k < N / 4; ++k)
-      cb.d[j][k] = __builtin_amdgcn_readfirstlane(rowp[k]);
+      cb.d[j][k] = __builtin_amdgcn_readfirstlane(ld_global<uint32_t>(rowp + k));
   }
 }
 

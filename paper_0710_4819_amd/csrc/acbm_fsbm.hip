@@ -72,7 +72,7 @@ __device__ __forceinline__ uint32_t wave_intra_x(const uint8_t* __restrict__ cur
   uint32_t d = 0;
   if (lane < D) {
     const int j = lane / (N / 4), k = lane % (N / 4);
-    d = *reinterpret_cast<const uint32_t*>(cur + (size_t)(y0 + j) * pitch + x0 + 4 * k);
+    d = ld_global<uint32_t>(cur + (size_t)(y0 + j) * pitch + x0 + 4 * k);
   }
   const uint32_t s = wave_sum_u32(__builtin_amdgcn_sad_u8(d, 0u, 0u));
   uint32_t a = 0;
@@ -334,7 +334,12 @@ k_search_batch(const BatchJob* __restrict__ jobs, int njobs, uint32_t items) {
   const uint32_t local = it - J.item0;
   const int pair = (int)(local / (uint32_t)g.nb), b = (int)(local % (uint32_t)g.nb);
   const size_t at = (size_t)pair * g.nb + b;
-  search_block<N, M, R, kKindFsbm>(g, J.s, J.frames[pair], J.frames[pair + 1], b, nullptr,
+  // the window shape by value: read through a reference, it would be
+  // reloaded after every LDS store that might alias it
+  const WindowShape s = J.s;
+  const uint8_t* ref = ld_global<const uint8_t*>(J.frames + pair);
+  const uint8_t* cur = ld_global<const uint8_t*>(J.frames + pair + 1);
+  search_block<N, M, R, kKindFsbm>(g, s, ref, cur, b, nullptr,
                                J.recs + at, J.ovf + at * ovf_stride(g.p), J.slack, win, red,
                                &n_keep);
 }
@@ -372,7 +377,7 @@ __device__ __forceinline__ void search_tile(const KGeom& g, const WindowShape& s
   // are sums over those 16 lanes
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x, b = lane >> 4, k = lane & 15;
-    const uint32_t d = *reinterpret_cast<const uint32_t*>(
+    const uint32_t d = ld_global<uint32_t>(
         cur + (size_t)(y0 + 8 * (b >> 1) + (k >> 1)) * g.pitch + x0 + 8 * (b & 1) + 4 * (k & 1));
     const uint32_t sum = group_sum<16>(__builtin_amdgcn_sad_u8(d, 0u, 0u));
     uint32_t a = 0;
@@ -511,7 +516,10 @@ k_search_batch_tile(const BatchJob* __restrict__ jobs, int njobs, uint32_t items
   const uint32_t nt = (uint32_t)g.nb >> 2;
   const uint32_t local = it - J.item0;
   const int pair = (int)(local / nt), t = (int)(local % nt);
-  search_tile<R>(g, J.s, J.frames[pair], J.frames[pair + 1], t, J.recs + (size_t)pair * g.nb,
+  const WindowShape s = J.s;  // by value, as in k_search_batch
+  const uint8_t* ref = ld_global<const uint8_t*>(J.frames + pair);
+  const uint8_t* cur = ld_global<const uint8_t*>(J.frames + pair + 1);
+  search_tile<R>(g, s, ref, cur, t, J.recs + (size_t)pair * g.nb,
                  J.ovf + (size_t)pair * g.nb * ovf_stride(g.p), J.slack, win, red, n_keep, intra);
 }
 
@@ -624,21 +632,23 @@ __device__ __forceinline__ uint64_t wave_block_argmin(const BlockRec* __restrict
       }
 #pragma unroll
       for (int k = 0; k < kPieces; ++k) {
+        // a guard, not a break: the loop stays unrolled and q[] in registers
         const int c = c0 + 64 * k;
-        if (c >= npieces) break;
-        const int pos = 8 * c;
-        int u = pos % W - p, v = pos / W - p;
-        const uint32_t w4[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
+        if (c < npieces) {
+          const int pos = 8 * c;
+          int u = pos % W - p, v = pos / W - p;
+          const uint32_t w4[4] = {q[k].x, q[k].y, q[k].z, q[k].w};
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const uint32_t sad = (w4[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
-          if (sad != 0xFFFFu && pos + e < WW) {
-            const uint64_t key = int_key<HP>(sad, u, v, p, px, py, lam);
-            best = key < best ? key : best;
-          }
-          if (++u > p) {
-            u = -p;
-            ++v;
+          for (int e = 0; e < 8; ++e) {
+            const uint32_t sad = (w4[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+            if (sad != 0xFFFFu && pos + e < WW) {
+              const uint64_t key = int_key<HP>(sad, u, v, p, px, py, lam);
+              best = key < best ? key : best;
+            }
+            if (++u > p) {
+              u = -p;
+              ++v;
+            }
           }
         }
       }
@@ -1315,30 +1325,35 @@ __device__ __forceinline__ void resolve_pair_sweeps(const KGeom& g,
 // decision state (LDS or workspace); `shared` two words of LDS.  HP:
 // half-pel precision (every block needs its predictor: anti-diagonal
 // steps); cur and ref are then the pair's frames.  Integer precision picks
-// sweeps when under a quarter of the blocks have several possible winners
-// and steps otherwise; both decide every block with its final predictor, so
-// the results do not depend on the choice.
+// sweeps when `sweeps` allows them and under a quarter of the blocks have
+// several possible winners, and steps otherwise.  (A sweep scans the whole
+// frame, so it wants every wave of a 1024-thread group; the steps need four
+// lanes per block row.)  Both decide every block with its final predictor,
+// so the results do not depend on the choice.
 template <bool HP>
 __device__ __forceinline__ void resolve_pair(const KGeom& g, const BlockRec* __restrict__ recs,
                                              const uint16_t* __restrict__ ovf,
                                              acbm_block_result* __restrict__ out, uint32_t lam,
                                              uint32_t* st, int* shared,
                                              const uint8_t* __restrict__ cur,
-                                             const uint8_t* __restrict__ ref) {
+                                             const uint8_t* __restrict__ ref, bool sweeps) {
   if constexpr (HP) {
     if (4 * g.by <= (int)blockDim.x)
       resolve_pair_half4(g, recs, ovf, out, lam, st, cur, ref);
     else
       resolve_pair_half(g, recs, ovf, out, lam, st, cur, ref);
   } else {
-    if (threadIdx.x == 0) shared[1] = 0;
-    __syncthreads();
-    int multi = 0;
-    for (int b = threadIdx.x; b < g.nb; b += blockDim.x) multi += recs[b].count > 1;
-    multi = (int)wave_sum_u32((uint32_t)multi);
-    if ((threadIdx.x & 63) == 0) atomicAdd(&shared[1], multi);
-    __syncthreads();
-    const int nmulti = __builtin_amdgcn_readfirstlane(shared[1]);
+    int nmulti = g.nb;
+    if (sweeps) {
+      if (threadIdx.x == 0) shared[1] = 0;
+      __syncthreads();
+      int multi = 0;
+      for (int b = threadIdx.x; b < g.nb; b += blockDim.x) multi += recs[b].count > 1;
+      multi = (int)wave_sum_u32((uint32_t)multi);
+      if ((threadIdx.x & 63) == 0) atomicAdd(&shared[1], multi);
+      __syncthreads();
+      nmulti = __builtin_amdgcn_readfirstlane(shared[1]);
+    }
     if (4 * nmulti < g.nb)
       resolve_pair_sweeps(g, recs, ovf, out, lam, st, shared);
     else if (4 * g.by <= (int)blockDim.x)
@@ -1368,9 +1383,9 @@ k_resolve(const KGeom g, const BlockRec* __restrict__ recs, const uint16_t* __re
   // pointer that may be either compiles to FLAT accesses, whose waits also
   // cover the record prefetch)
   if (st_global)
-    resolve_pair<HP>(g, r, o, res, lam, st_global + (size_t)pair * g.nb, shared, cur, ref);
+    resolve_pair<HP>(g, r, o, res, lam, st_global + (size_t)pair * g.nb, shared, cur, ref, true);
   else
-    resolve_pair<HP>(g, r, o, res, lam, st_lds, shared, cur, ref);
+    resolve_pair<HP>(g, r, o, res, lam, st_lds, shared, cur, ref, true);
 }
 
 // Half-pel SADs prepared off the resolve's sequential path.  For every block
@@ -1467,7 +1482,7 @@ k_half_prep(const KGeom g, const FramePtrs fr, int npairs, BlockRec* __restrict_
 // The resolves of every pair of a set of FSBM jobs: one workgroup per pair,
 // workgroup k resolving pair k + pair_base of the numbering by pair0.
 __global__ void __launch_bounds__(1024)
-k_resolve_batch(const BatchJob* __restrict__ jobs, int njobs, uint32_t pair_base) {
+k_resolve_batch(const BatchJob* __restrict__ jobs, int njobs, uint32_t pair_base, bool sweeps) {
   extern __shared__ uint32_t st_lds[];
   __shared__ int shared[2];
   const uint32_t wg = blockIdx.x + pair_base;
@@ -1493,14 +1508,14 @@ k_resolve_batch(const BatchJob* __restrict__ jobs, int njobs, uint32_t pair_base
   if (__builtin_amdgcn_readfirstlane(J.mv_ws != nullptr)) {
     uint32_t* st = J.mv_ws + (size_t)pair * g.nb;
     if (hp)
-      resolve_pair<true>(g, recs, ovf, out, J.lam, st, shared, cur, ref);
+      resolve_pair<true>(g, recs, ovf, out, J.lam, st, shared, cur, ref, sweeps);
     else
-      resolve_pair<false>(g, recs, ovf, out, J.lam, st, shared, nullptr, nullptr);
+      resolve_pair<false>(g, recs, ovf, out, J.lam, st, shared, nullptr, nullptr, sweeps);
   } else {
     if (hp)
-      resolve_pair<true>(g, recs, ovf, out, J.lam, st_lds, shared, cur, ref);
+      resolve_pair<true>(g, recs, ovf, out, J.lam, st_lds, shared, cur, ref, sweeps);
     else
-      resolve_pair<false>(g, recs, ovf, out, J.lam, st_lds, shared, nullptr, nullptr);
+      resolve_pair<false>(g, recs, ovf, out, J.lam, st_lds, shared, nullptr, nullptr, sweeps);
   }
 }
 
@@ -1667,14 +1682,27 @@ int launch_search_batch(int N, int M, const SearchPlan& pl, size_t lds, const Ba
   return fail(ACBM_E_UNSUPPORTED, "block size must be 8 or 16 in each direction");
 }
 
+// Threads of a batch resolve workgroup: four per block row, so that every
+// pair takes the four-lanes-per-block steps (resolve_pair_int4), and no more.
+// The resolve runs beside later searches, and each of its waves holds about
+// a quarter of a SIMD's registers: a 1024-thread group leaves its CU no room
+// for search waves.  Such a group resolves by steps only.  Frames of more
+// than 256 block rows take 1024 threads (one per block row of a step).
+static int resolve_threads(int max_by) {
+  const int t = (4 * max_by + 63) / 64 * 64;
+  return t > 1024 ? 1024 : (t < 256 ? 256 : t);
+}
+
 int launch_resolve_batch(const BatchJob* jobs, int njobs, uint32_t pair_base, uint32_t pairs,
-                         size_t lds, hipStream_t st) {
+                         size_t lds, int max_by, hipStream_t st) {
   if (!pairs) return ACBM_OK;
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute((const void*)k_resolve_batch,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   ProfScope ps("resolve", st);
-  hipLaunchKernelGGL(k_resolve_batch, dim3(pairs), dim3(1024), lds, st, jobs, njobs, pair_base);
+  const int threads = resolve_threads(max_by);
+  hipLaunchKernelGGL(k_resolve_batch, dim3(pairs), dim3(threads), lds, st, jobs, njobs, pair_base,
+                     threads == 1024);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? ACBM_OK : hip_fail(e, "launching the batched resolve");
 }
