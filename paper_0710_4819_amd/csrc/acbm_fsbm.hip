@@ -116,6 +116,9 @@ __device__ __forceinline__ uint64_t keep_mask(const uint64_t (&acc)[R], uint32_t
 // Stores the kept candidates of a task at dst[slot], dst[slot + 1], ... as
 // (SAD << 16 | window raster index): one loop turn per kept candidate, the
 // candidate's accumulator picked by a select chain (no dynamic register index).
+// The stores are typed global: through a generic pointer (the batch kernels
+// take theirs from the job table) they would be FLAT stores, which also hold
+// up the next LDS wait.
 template <int R>
 __device__ __forceinline__ void write_kept(const uint64_t (&acc)[R], uint64_t keep, uint32_t slot,
                                            uint32_t* __restrict__ dst, int u0, int v0, int p,
@@ -128,7 +131,7 @@ __device__ __forceinline__ void write_kept(const uint64_t (&acc)[R], uint64_t ke
 #pragma unroll
     for (int r = 1; r < R; ++r) a = rr == r ? acc[r] : a;
     const uint32_t sad = (uint32_t)(a >> (16 * i)) & 0xFFFFu;
-    dst[slot++] = (sad << 16) | (uint32_t)((v0 + rr + p) * W + (u0 + i + p));
+    st_global<uint32_t>(dst + slot++, (sad << 16) | (uint32_t)((v0 + rr + p) * W + (u0 + i + p)));
   }
 }
 
@@ -266,14 +269,14 @@ __device__ __forceinline__ void search_block(const KGeom& g, const WindowShape& 
       for (int i = 0; i < 4; ++i) {
         const int u = u0 + i;
         if (u < -p || u > p) continue;
-        row[(v + p) * W + (u + p)] = (uint16_t)(acc[rr] >> (16 * i));
+        st_global<uint16_t>(row + (v + p) * W + (u + p), (uint16_t)(acc[rr] >> (16 * i)));
       }
     }
   }
   if (threadIdx.x == 0) {
-    rec->sad_min = smin;
-    rec->count = total;
-    rec->intra_x = intra;
+    st_global<uint32_t>(&rec->sad_min, smin);
+    st_global<uint32_t>(&rec->count, total);
+    st_global<uint32_t>(&rec->intra_x, intra);
   }
 }
 
@@ -468,15 +471,15 @@ __device__ __forceinline__ void search_tile(const KGeom& g, const WindowShape& s
         for (int i = 0; i < 4; ++i) {
           const int u = u0 + i;
           if (u < -p || u > p) continue;
-          row[(v + p) * W + (u + p)] = (uint16_t)(acc[b][rr] >> (16 * i));
+          st_global<uint16_t>(row + (v + p) * W + (u + p), (uint16_t)(acc[b][rr] >> (16 * i)));
         }
       }
     }
     if (threadIdx.x == 0) {
       BlockRec* __restrict__ rec = recs + blk;
-      rec->sad_min = smin[b];
-      rec->count = total;
-      rec->intra_x = intra[b];
+      st_global<uint32_t>(&rec->sad_min, smin[b]);
+      st_global<uint32_t>(&rec->count, total);
+      st_global<uint32_t>(&rec->intra_x, intra[b]);
     }
   }
 }
@@ -578,7 +581,8 @@ __device__ __forceinline__ uint64_t wave_block_argmin(const BlockRec* __restrict
                                                       const uint16_t* __restrict__ row, int p,
                                                       int px, int py, uint32_t lam) {
   const int lane = threadIdx.x & 63;
-  const uint32_t w = lane < 32 ? reinterpret_cast<const uint32_t*>(rec)[lane] : 0u;
+  const uint32_t w =
+      lane < 32 ? ld_global<uint32_t>(reinterpret_cast<const uint32_t*>(rec) + lane) : 0u;
   const uint32_t n = (uint32_t)__shfl((int)w, 1, 64);  // rec->count
   uint64_t best = ~0ull;
   if (n > (uint32_t)kShort && n <= ovf_list_cap(p)) {
@@ -595,7 +599,7 @@ __device__ __forceinline__ uint64_t wave_block_argmin(const BlockRec* __restrict
 #pragma unroll
       for (int t = 0; t < kList; ++t) {
         const uint32_t k = k0 + 64u * t;
-        e[t] = k < n ? list[k] : 0u;
+        e[t] = k < n ? ld_global<uint32_t>(list + k) : 0u;
       }
 #pragma unroll
       for (int t = 0; t < kList; ++t) {
@@ -628,7 +632,11 @@ __device__ __forceinline__ uint64_t wave_block_argmin(const BlockRec* __restrict
 #pragma unroll
       for (int k = 0; k < kPieces; ++k) {
         const int c = c0 + 64 * k;
-        q[k] = c < npieces ? row4[c] : make_uint4(~0u, ~0u, ~0u, ~0u);
+        q[k] = make_uint4(~0u, ~0u, ~0u, ~0u);
+        if (c < npieces) {
+          const u32x4 t = ld_global_x4(row4 + c);
+          q[k] = make_uint4(t.x, t.y, t.z, t.w);
+        }
       }
 #pragma unroll
       for (int k = 0; k < kPieces; ++k) {
