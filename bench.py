@@ -46,11 +46,11 @@ PEAK_TEVALS = 256 * 64 * 2.4e9 * 4 / 1e12
 # `bench.py --steps 1 --warmup 0 --no-cpu --only fsbm --calib-copy-mib 256`:
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of k_search<16,16,6,false>,
 # each scaled by what the same counter reads for the 256 MiB device copy in
-# that run (FETCH_SIZE reads 131090.9 KiB for 262144 KiB moved, WRITE_SIZE
+# that run (FETCH_SIZE reads 131091.3 KiB for 262144 KiB moved, WRITE_SIZE
 # 262144 KiB).  Valid for the kernel these counters were taken on; set to
 # None when the search kernel changes.
-SEARCH_TRAFFIC = {"kernel": "k_search<16,16,6,false>", "fetch_kib": 147170.7,
-                  "write_kib": 31368.5, "fetch_scale": 262144.0 / 131090.9, "write_scale": 1.0}
+SEARCH_TRAFFIC = {"kernel": "k_search<16,16,6,false>", "fetch_kib": 147165.6,
+                  "write_kib": 15802.1, "fetch_scale": 262144.0 / 131091.3, "write_scale": 1.0}
 
 
 def search_traffic_bytes():

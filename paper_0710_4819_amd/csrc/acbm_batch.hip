@@ -602,8 +602,12 @@ int enqueue_fsbm(const acbm_job* jobs, const Plan& pl, char* base, const BatchJo
         lds = std::max(lds, pl.classes[k].lds_resolve);
         max_by = std::max(max_by, pl.classes[k].max_by);
       }
+      // with several classes every resolve is sized: all but the last run
+      // beside later searches, and the last one, on the mixed batch, steps
+      // faster than it sweeps
       if ((rc = launch_resolve_batch(all + pend_jo, (int)(jo - pend_jo), c0.pair0,
-                                     c.pair0 + c.pairs - c0.pair0, lds, max_by, to)))
+                                     c.pair0 + c.pairs - c0.pair0, lds, max_by,
+                                     pl.classes.size() > 1, to)))
         return rc;
       pend = ci + 1;
       pend_jo = jo;
@@ -611,7 +615,7 @@ int enqueue_fsbm(const acbm_job* jobs, const Plan& pl, char* base, const BatchJo
   }
   if (!nrs && pl.njob_fsbm &&
       (rc = launch_resolve_batch(all, (int)pl.njob_fsbm, 0, pl.pairs, pl.lds_resolve, pl.max_by,
-                                 st)))
+                                 false, st)))
     return rc;
   return ACBM_OK;
 }

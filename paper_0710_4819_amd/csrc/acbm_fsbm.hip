@@ -1690,25 +1690,28 @@ int launch_search_batch(int N, int M, const SearchPlan& pl, size_t lds, const Ba
   return fail(ACBM_E_UNSUPPORTED, "block size must be 8 or 16 in each direction");
 }
 
-// Threads of a batch resolve workgroup: four per block row, so that every
-// pair takes the four-lanes-per-block steps (resolve_pair_int4), and no more.
-// The resolve runs beside later searches, and each of its waves holds about
-// a quarter of a SIMD's registers: a 1024-thread group leaves its CU no room
-// for search waves.  Such a group resolves by steps only.  Frames of more
-// than 256 block rows take 1024 threads (one per block row of a step).
-static int resolve_threads(int max_by) {
+// Threads of a batch resolve workgroup.  Alone on the device, 1024, so that
+// pairs with few several-winner blocks can take sweeps.  Beside other
+// searches (`sized`), four per block row of the tallest frame, so that every
+// pair takes the four-lanes-per-block steps (resolve_pair_int4), and no
+// more: each wave holds about a quarter of a SIMD's registers, and a
+// 1024-thread group leaves its CU no room for search waves.  Such a group
+// resolves by steps only.  Frames of more than 256 block rows take 1024
+// threads (one per block row of a step).
+static int resolve_threads(int max_by, bool sized) {
+  if (!sized) return 1024;
   const int t = (4 * max_by + 63) / 64 * 64;
   return t > 1024 ? 1024 : (t < 256 ? 256 : t);
 }
 
 int launch_resolve_batch(const BatchJob* jobs, int njobs, uint32_t pair_base, uint32_t pairs,
-                         size_t lds, int max_by, hipStream_t st) {
+                         size_t lds, int max_by, bool sized, hipStream_t st) {
   if (!pairs) return ACBM_OK;
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute((const void*)k_resolve_batch,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   ProfScope ps("resolve", st);
-  const int threads = resolve_threads(max_by);
+  const int threads = resolve_threads(max_by, sized);
   hipLaunchKernelGGL(k_resolve_batch, dim3(pairs), dim3(threads), lds, st, jobs, njobs, pair_base,
                      threads == 1024);
   hipError_t e = hipGetLastError();

@@ -191,10 +191,11 @@ int batch_enqueue(const acbm_job* jobs, size_t njobs, const acbm_mv* const* prev
                   std::vector<const uint32_t*>* status_words);
 // Resolves pairs pair_base .. pair_base + pairs - 1 (numbered by pair0) of
 // the `njobs` jobs at `jobs`, which must hold every job with such a pair;
-// max_by is the most block rows of those pairs' frames (it sizes the
-// workgroup).
+// max_by is the most block rows of those pairs' frames.  `sized`: the
+// resolve runs beside other searches, and its workgroups are sized to the
+// frames (see resolve_threads).
 int launch_resolve_batch(const BatchJob* jobs, int njobs, uint32_t pair_base, uint32_t pairs,
-                         size_t lds, int max_by, hipStream_t s);
+                         size_t lds, int max_by, bool sized, hipStream_t s);
 size_t predictive_ws_bytes(const KGeom& g, uint32_t npairs);
 int launch_predictive(const KGeom& g, const acbm_params& prm, int algo,
                       const uint8_t* const* frames, uint32_t npairs, const acbm_mv* prev_field,
