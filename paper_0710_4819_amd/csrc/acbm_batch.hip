@@ -353,6 +353,14 @@ int side_streams() {
   return std::max(0, std::min(kSideStreams, std::atoi(e)));
 }
 
+// Whether the resolves of a batch with several search classes get sized
+// workgroups (launch_resolve_batch): ACBM_BATCH_RESOLVE_SIZED=0 keeps
+// 1024-thread groups, which may sweep.  Read at every call.
+bool resolve_sized() {
+  const char* e = std::getenv("ACBM_BATCH_RESOLVE_SIZED");
+  return !(e && e[0] == '0');
+}
+
 // The side streams of device `dev`, the current device; g_side_mu is held.
 int side_pool(int dev, SidePool** out) {
   auto it = g_side.find(dev);
@@ -607,7 +615,7 @@ int enqueue_fsbm(const acbm_job* jobs, const Plan& pl, char* base, const BatchJo
       // faster than it sweeps
       if ((rc = launch_resolve_batch(all + pend_jo, (int)(jo - pend_jo), c0.pair0,
                                      c.pair0 + c.pairs - c0.pair0, lds, max_by,
-                                     pl.classes.size() > 1, to)))
+                                     pl.classes.size() > 1 && resolve_sized(), to)))
         return rc;
       pend = ci + 1;
       pend_jo = jo;
