@@ -337,8 +337,10 @@ k_search_batch(const BatchJob* __restrict__ jobs, int njobs, uint32_t items) {
   const uint32_t local = it - J.item0;
   const int pair = (int)(local / (uint32_t)g.nb), b = (int)(local % (uint32_t)g.nb);
   const size_t at = (size_t)pair * g.nb + b;
-  // the window shape by value: read through a reference, it would be
-  // reloaded after every LDS store that might alias it
+  // The window shape by value: read through a reference, it would be
+  // reloaded after every LDS store that might alias it.  The frames are read
+  // with global loads (load_window, load_cur_uniform), so the current block
+  // lands in scalar registers as in k_search.
   const WindowShape s = J.s;
   const uint8_t* ref = ld_global<const uint8_t*>(J.frames + pair);
   const uint8_t* cur = ld_global<const uint8_t*>(J.frames + pair + 1);
